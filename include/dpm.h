@@ -1,0 +1,170 @@
+/*
+ * libdpm -- 3D geometric moments of uint8/uint16 volumes on AMD Instinct MI355X
+ * (gfx950) with the Discrete Projection Moment method of Diggin & Diggin,
+ * "Fast 3D Image Moments" (arXiv 2012.08099).
+ *
+ * What is computed (Section 1, eq. 2):
+ *     M_pqr = sum_{x,y,z} V(x,y,z) x^p y^q z^r,   0 <= x < L, 0 <= y < M, 0 <= z < N,
+ * for every p+q+r <= max_order (0 <= max_order <= 16), with 0^0 = 1.
+ *
+ * How (Section 3): one pass over the volume forms max_order+1 integer projection
+ * images I_d(i, y) = sum over alpha_d x + beta_d z = i of V (eq. 4; the directions
+ * (1,0), (0,1), (1,1), (1,-1) are eqs. 5, 6, 8, 9 and the rest are the further
+ * aligned projections listed after eq. 9); the 2D power moments of every image are
+ * taken (eq. 1); the 3D moments are recovered from them by the recombination of
+ * Section 3.2 (eqs. 10-16, generalised to any order).  All arithmetic after the
+ * volume read is exact integer arithmetic; orders <= 4 are returned as exact 128-bit
+ * integers and every order as the nearest FP64 value of the exact integer.
+ *
+ * Volume layout: contiguous V[z][y][x] (x fastest), element type uint8 or uint16,
+ * resident in device memory.  dims = {L, M, N} = {X, Y, Z} extents.
+ *
+ * Moment order in every output array ("graded order"): p+q+r ascending; within one
+ * total order p descending, then q descending:
+ *     M000; M100 M010 M001; M200 M110 M101 M020 M011 M002; ...
+ *
+ * Conventions for every function below:
+ *   - return 0 (DPM_OK) on success or a negative dpm_status; never throw or abort;
+ *   - "device pointer" = memory from hipMalloc (or torch) on the current device;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream);
+ *   - the library keeps no caller pointer after a call (async: after the stream work
+ *     it enqueued has finished);
+ *   - calls that enqueue on the same stream are ordered; calls on different streams
+ *     must use different workspaces.
+ */
+#ifndef DPM_H
+#define DPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DPM_OK = 0,
+    DPM_EINVAL = -1,   /* null pointer, dim <= 0, unknown dtype, order outside [0,16], bad size */
+    DPM_ERANGE = -2,   /* volume too large for the exact integer widths the library provides */
+    DPM_ENOMEM = -3,   /* workspace too small, or device/host allocation failed              */
+    DPM_EDEVICE = -4,  /* a HIP runtime error; see dpm_last_device_error()                   */
+    DPM_ENOTSUP = -5   /* valid request the library does not implement                       */
+} dpm_status;
+
+typedef enum { DPM_U8 = 1, DPM_U16 = 2 } dpm_dtype;
+
+/* Two's complement signed 128-bit integer, little-endian words. */
+typedef struct {
+    uint64_t lo;
+    int64_t hi;
+} dpm_i128;
+
+/* Result buffers (caller-owned; host or device memory depending on the call).
+ *   exact: dpm_num_moments(min(max_order, 4)) entries -- orders 0..4, exact;
+ *          may be NULL if not wanted.
+ *   fp64:  dpm_num_moments(max_order) entries -- every order, each the FP64 value
+ *          nearest to the exact integer moment (ties to even); may be NULL. */
+typedef struct {
+    dpm_i128 *exact;
+    double *fp64;
+} dpm_out;
+
+/* Number of moments with p+q+r <= max_order: (K+1)(K+2)(K+3)/6; -1 if K outside [0,16]. */
+int dpm_num_moments(int max_order);
+
+/* Graded-order position of (p,q,r); -1 if any index is negative or p+q+r > 16. */
+int dpm_moment_index(int p, int q, int r);
+
+/* Static description of an error code. */
+const char *dpm_strerror(int status);
+
+/* hipError_t of the most recent DPM_EDEVICE on this thread (0 if none). */
+int dpm_last_device_error(void);
+
+/* Projection direction d (0 <= d <= 16) of the fixed family used for order
+ * max_order = d and above: image d sums V along alpha x + beta z = const. */
+int dpm_direction(int d, int *alpha, int *beta);
+
+/* Width of projection image d for a volume of the given dims:
+ * alpha (L-1) + |beta| (N-1) + 1; 0 on invalid input. */
+int64_t dpm_image_width(const int64_t dims[3], int d);
+
+/* Device workspace needed by dpm_moments_async for this request (bytes); 0 if the
+ * request is invalid. */
+size_t dpm_workspace_bytes(const int64_t dims[3], dpm_dtype dtype, int max_order);
+
+/* Blocking convenience call.  volume: device pointer.  out->exact / out->fp64: HOST
+ * memory.  Uses a library-owned workspace (cached per device, freed by dpm_release). */
+int dpm_moments(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order,
+                dpm_out *out);
+
+/* Stream-ordered call.  volume, out_device->exact/fp64 and workspace are device
+ * pointers; workspace must hold dpm_workspace_bytes() bytes (NULL = use the
+ * library-owned workspace of this device, which serialises callers).  Returns after
+ * enqueueing; results are valid once `stream` reaches this point. */
+int dpm_moments_async(const void *volume, const int64_t dims[3], dpm_dtype dtype,
+                      int max_order, const dpm_out *out_device, void *workspace,
+                      size_t ws_bytes, void *stream);
+
+/* The max_order+1 projection images of Section 3.1 (step 1 of the method), exact
+ * int32.  images_device: device pointer to sum_d M * width_d int32 values; image d is
+ * stored row-major as [y][i] right after image d-1.  For beta < 0 the column index
+ * carries the offset |beta| (N-1) (column x - z + N - 1 for the (1,-1) image, as in
+ * the projection pseudo-code of Section 5).  Requires every line sum to fit in
+ * 32 bits (else DPM_ERANGE). */
+int dpm_project_images(const void *volume, const int64_t dims[3], dpm_dtype dtype,
+                       int max_order, int32_t *images_device, void *stream);
+
+/* ---- batched regions of interest --------------------------------------------
+ * Many independent volumes ("ROIs") in one packed device buffer; each ROI is its own
+ * volume with its own origin (eq. 2 applied to the ROI).  ROI i starts at byte
+ * offset rois[i].offset_bytes of `packed`, holds dims[0]*dims[1]*dims[2] elements of
+ * rois[i].dtype in V[z][y][x] order.  Rows start 16-byte aligned and whole rows are
+ * readable when (offset_bytes % 16 == 0 and L*elem % 16 == 0); otherwise the ROI is
+ * read with narrower loads (correct, slower). */
+typedef struct {
+    uint64_t offset_bytes;
+    int64_t dims[3];
+    int32_t dtype; /* dpm_dtype */
+    int32_t reserved;
+} dpm_roi;
+
+size_t dpm_batched_workspace_bytes(const dpm_roi *rois, int n_rois, int max_order);
+
+/* All ROIs in one persistent launch sequence.  out_device->exact / ->fp64 hold
+ * n_rois consecutive result blocks (block i at i * dpm_num_moments(...)). */
+int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int max_order,
+                        const dpm_out *out_device, void *workspace, size_t ws_bytes,
+                        void *stream);
+
+/* Free every library-owned device workspace and cached plan. */
+int dpm_release(void);
+
+/* ---- introspection used by the host-side tests ------------------------------ */
+
+/* Exact recombination weight of Section 3.2 generalised: for total x-z degree k,
+ *   M_{p, q, k-p} = sum_{d<=k} num[p][d] * m_d / den[p]
+ * where m_d is the degree-(k, q) 2D moment of image d about its true origin.
+ * Writes num (int64) and den (uint64, > 0) for one (k, p, d). */
+int dpm_recomb_weight(int k, int p, int d, int64_t *num, uint64_t *den);
+
+/* Planning summary for a request (host logic only; no device work). */
+typedef struct {
+    int32_t n_dirs;        /* max_order + 1                                   */
+    int32_t n_groups;      /* launches of the projection kernel               */
+    int32_t n_items;       /* workgroups per launch (y-slices x z-splits)     */
+    int32_t z_splits;      /* z-splits per y-slice                            */
+    int32_t limbs_slice;   /* 32-bit limbs of per-slice partial sums          */
+    int32_t limbs_moment;  /* 32-bit limbs of 2D moments and recombination    */
+    int32_t bits_slice;    /* bound on partial sums (bits incl. sign)         */
+    int32_t bits_moment;   /* bound on recombination numerators (bits)        */
+    int64_t lds_bytes;     /* LDS per projection workgroup (largest group)    */
+    int64_t workspace;     /* bytes                                           */
+} dpm_plan_info;
+
+int dpm_plan(const int64_t dims[3], dpm_dtype dtype, int max_order, dpm_plan_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPM_H */

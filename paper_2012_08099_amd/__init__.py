@@ -1,0 +1,212 @@
+"""3D geometric moments on MI355X with the Discrete Projection Moment method.
+
+Diggin & Diggin, "Fast 3D Image Moments" (arXiv 2012.08099).  The moments
+M_pqr = sum V(x,y,z) x^p y^q z^r (Section 1, eq. 2) of a uint8/uint16 volume are
+computed by HIP kernels for gfx950 behind the C ABI of ``include/dpm.h``; this module
+only marshals arguments (torch supplies device memory and streams).
+
+Volumes are torch tensors of shape (N, M, L) = (z, y, x) on a ROCm device, dtype
+torch.uint8 or torch.uint16, contiguous.  Moments come in graded order (p+q+r
+ascending, then p descending, then q descending); see ``moment_list``.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import DpmError, Dims, I128, Out, PlanInfo, Roi, check, lib
+
+__all__ = [
+    "DpmError", "Moments", "moment_list", "num_moments", "moment_index", "direction", "image_width",
+    "workspace_bytes", "plan", "moments", "moments_async", "project_images", "moments_batched",
+    "batched_workspace_bytes", "pack_rois", "recomb_weight", "release",
+]
+
+KMAX = 16
+
+
+def moment_list(K):
+    """(p, q, r) in graded order for p+q+r <= K."""
+    out = []
+    for n in range(K + 1):
+        for p in range(n, -1, -1):
+            for q in range(n - p, -1, -1):
+                out.append((p, q, n - p - q))
+    return out
+
+
+def num_moments(K):
+    return int(lib().dpm_num_moments(int(K)))
+
+
+def moment_index(p, q, r):
+    return int(lib().dpm_moment_index(p, q, r))
+
+
+def direction(d):
+    a, b = ctypes.c_int(), ctypes.c_int()
+    check(lib().dpm_direction(d, ctypes.byref(a), ctypes.byref(b)), "dpm_direction")
+    return a.value, b.value
+
+
+def _dims_of_shape(shape):
+    N, M, L = (int(s) for s in shape)
+    return Dims(L, M, N)
+
+
+def image_width(shape, d):
+    return int(lib().dpm_image_width(_dims_of_shape(shape), d))
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.uint8:
+        return _lib.DPM_U8
+    if t.dtype in (torch.uint16, torch.int16):
+        return _lib.DPM_U16
+    raise TypeError(f"unsupported volume dtype {t.dtype}; use torch.uint8 or torch.uint16")
+
+
+def _check_volume(vol):
+    if not vol.is_cuda:
+        raise ValueError("volume must be a device (ROCm) tensor")
+    if vol.dim() != 3:
+        raise ValueError("volume must have shape (N, M, L) = (z, y, x)")
+    if not vol.is_contiguous():
+        raise ValueError("volume must be contiguous")
+
+
+def workspace_bytes(shape, dtype_code, K):
+    return int(lib().dpm_workspace_bytes(_dims_of_shape(shape), dtype_code, K))
+
+
+def plan(shape, dtype_code, K):
+    info = PlanInfo()
+    check(lib().dpm_plan(_dims_of_shape(shape), dtype_code, K, ctypes.byref(info)), "dpm_plan")
+    return {f: getattr(info, f) for f, _ in PlanInfo._fields_}
+
+
+def i128_to_int(lo, hi):
+    return int(lo) | (int(hi) << 64)
+
+
+@dataclass
+class Moments:
+    """Result of one volume: ``exact`` = orders <= min(K, 4) as Python ints; ``fp64`` =
+    every order as float64 (nearest to the exact integer)."""
+    K: int
+    exact: list
+    fp64: np.ndarray
+
+    def as_dict(self):
+        return dict(zip(moment_list(self.K), self.fp64.tolist()))
+
+
+def _exact_from_tensor(ex):
+    a = ex.view(-1, 2).cpu().numpy()
+    return [int(lo) | (int(hi) << 64) for lo, hi in zip(a[:, 0].astype(np.uint64).tolist(),
+                                                       a[:, 1].astype(np.int64).tolist())]
+
+
+def moments(vol, K, stream=None):
+    """Moments of one volume (blocking).  Returns ``Moments``."""
+    import torch
+    _check_volume(vol)
+    nm, nm4 = num_moments(K), num_moments(min(K, 4))
+    if nm < 0:
+        raise ValueError("max_order must be in [0, 16]")
+    dev = vol.device
+    ex = torch.empty((nm4, 2), dtype=torch.int64, device=dev)
+    fp = torch.empty(nm, dtype=torch.float64, device=dev)
+    ws_n = workspace_bytes(vol.shape, _dtype_code(vol), K)
+    if ws_n == 0:
+        check(-2, "dpm_workspace_bytes")
+    ws = torch.empty(ws_n, dtype=torch.uint8, device=dev)
+    moments_async(vol, K, ex, fp, ws, stream)
+    (stream or torch.cuda.current_stream(dev)).synchronize()
+    return Moments(K, _exact_from_tensor(ex), fp.cpu().numpy())
+
+
+def moments_async(vol, K, out_exact, out_fp64, workspace, stream=None):
+    """Enqueue on ``stream`` (default: current).  Outputs/workspace are device tensors."""
+    import torch
+    _check_volume(vol)
+    st = stream if stream is not None else torch.cuda.current_stream(vol.device)
+    out = Out(out_exact.data_ptr() if out_exact is not None else None,
+              out_fp64.data_ptr() if out_fp64 is not None else None)
+    rc = lib().dpm_moments_async(ctypes.c_void_p(vol.data_ptr()), _dims_of_shape(vol.shape), _dtype_code(vol),
+                                 int(K), ctypes.byref(out),
+                                 ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None,
+                                 workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                 ctypes.c_void_p(st.cuda_stream))
+    check(rc, "dpm_moments_async")
+
+
+def project_images(vol, K, stream=None):
+    """The K+1 projection images as a list of int32 device tensors of shape (M, W_d)."""
+    import torch
+    _check_volume(vol)
+    N, M, L = vol.shape
+    widths = [image_width(vol.shape, d) for d in range(K + 1)]
+    buf = torch.zeros(sum(w * M for w in widths), dtype=torch.int32, device=vol.device)
+    st = stream if stream is not None else torch.cuda.current_stream(vol.device)
+    rc = lib().dpm_project_images(ctypes.c_void_p(vol.data_ptr()), _dims_of_shape(vol.shape), _dtype_code(vol),
+                                  int(K), ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(st.cuda_stream))
+    check(rc, "dpm_project_images")
+    out, off = [], 0
+    for w in widths:
+        out.append(buf[off:off + w * M].view(M, w))
+        off += w * M
+    return out
+
+
+def pack_rois(volumes, device, align=16):
+    """Pack a list of numpy (N, M, L) uint8/uint16 arrays into one device buffer.
+
+    Returns (packed uint8 tensor, ctypes array of Roi descriptors)."""
+    import torch
+    offs, total = [], 0
+    for v in volumes:
+        total = (total + align - 1) // align * align
+        offs.append(total)
+        total += v.nbytes
+    host = np.zeros(max(total, 1), dtype=np.uint8)
+    rois = (Roi * len(volumes))()
+    for i, (v, o) in enumerate(zip(volumes, offs)):
+        v = np.ascontiguousarray(v)
+        host[o:o + v.nbytes] = v.view(np.uint8).reshape(-1)
+        N, M, L = v.shape
+        rois[i].offset_bytes = o
+        rois[i].dims[0], rois[i].dims[1], rois[i].dims[2] = L, M, N
+        rois[i].dtype = _lib.DPM_U8 if v.dtype == np.uint8 else _lib.DPM_U16
+    return torch.from_numpy(host).to(device), rois
+
+
+def batched_workspace_bytes(rois, K):
+    return int(lib().dpm_batched_workspace_bytes(rois, len(rois), int(K)))
+
+
+def moments_batched(packed, rois, K, out_exact, out_fp64, workspace, stream=None):
+    """All ROIs in one launch sequence; outputs are device tensors of n_rois blocks."""
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream(packed.device)
+    out = Out(out_exact.data_ptr() if out_exact is not None else None,
+              out_fp64.data_ptr() if out_fp64 is not None else None)
+    rc = lib().dpm_moments_batched(ctypes.c_void_p(packed.data_ptr()), rois, len(rois), int(K),
+                                   ctypes.byref(out), ctypes.c_void_p(workspace.data_ptr()),
+                                   workspace.numel() * workspace.element_size(),
+                                   ctypes.c_void_p(st.cuda_stream))
+    check(rc, "dpm_moments_batched")
+
+
+def recomb_weight(k, p, d):
+    n, den = ctypes.c_int64(), ctypes.c_uint64()
+    check(lib().dpm_recomb_weight(k, p, d, ctypes.byref(n), ctypes.byref(den)), "dpm_recomb_weight")
+    return n.value, den.value
+
+
+def release():
+    check(lib().dpm_release(), "dpm_release")

@@ -1,0 +1,106 @@
+"""ctypes binding of libdpm.so (argument marshalling only).
+
+Every computation runs in the HIP kernels behind the C ABI of ``include/dpm.h``.
+There is no CPU fallback: if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpm.so")
+
+DPM_U8 = 1
+DPM_U16 = 2
+
+STATUS = {0: "DPM_OK", -1: "DPM_EINVAL", -2: "DPM_ERANGE", -3: "DPM_ENOMEM", -4: "DPM_EDEVICE",
+          -5: "DPM_ENOTSUP"}
+
+
+class DpmError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        msg = f"{where}: {STATUS.get(status, status)}"
+        try:
+            msg += f" ({lib().dpm_strerror(status).decode()})"
+            if status == -4:
+                msg += f" hipError={lib().dpm_last_device_error()}"
+        except Exception:  # pragma: no cover - error while formatting an error
+            pass
+        super().__init__(msg)
+
+
+class I128(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_int64)]
+
+
+class Out(ctypes.Structure):
+    _fields_ = [("exact", ctypes.c_void_p), ("fp64", ctypes.c_void_p)]
+
+
+class Roi(ctypes.Structure):
+    _fields_ = [("offset_bytes", ctypes.c_uint64), ("dims", ctypes.c_int64 * 3),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_dirs", ctypes.c_int32), ("n_groups", ctypes.c_int32), ("n_items", ctypes.c_int32),
+                ("z_splits", ctypes.c_int32), ("limbs_slice", ctypes.c_int32),
+                ("limbs_moment", ctypes.c_int32), ("bits_slice", ctypes.c_int32),
+                ("bits_moment", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
+                ("workspace", ctypes.c_int64)]
+
+
+Dims = ctypes.c_int64 * 3
+
+# exported symbol -> (restype, argtypes)
+SIGNATURES = {
+    "dpm_num_moments": (ctypes.c_int, [ctypes.c_int]),
+    "dpm_moment_index": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "dpm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "dpm_last_device_error": (ctypes.c_int, []),
+    "dpm_direction": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "dpm_image_width": (ctypes.c_int64, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int]),
+    "dpm_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int]),
+    "dpm_moments": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                   ctypes.c_int, ctypes.POINTER(Out)]),
+    "dpm_moments_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                         ctypes.c_int, ctypes.POINTER(Out), ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.c_void_p]),
+    "dpm_project_images": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "dpm_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Roi), ctypes.c_int, ctypes.c_int]),
+    "dpm_moments_batched": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Roi), ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(Out), ctypes.c_void_p, ctypes.c_size_t,
+                                           ctypes.c_void_p]),
+    "dpm_release": (ctypes.c_int, []),
+    "dpm_recomb_weight": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]),
+    "dpm_plan": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(PlanInfo)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libdpm.so (built in-tree by ``build.py``); raise if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2012_08099_amd.build` "
+                "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status, where):
+    if status != 0:
+        raise DpmError(status, where)

@@ -73,7 +73,8 @@ def ct_phantom(shape=(512, 512, 512), seed=0, vmax=4095, slab=32):
 
     Air U{0..50} outside a centred body ellipsoid (semi-axes 0.45/0.35/0.45 of the
     z/y/x dimensions), tissue N(1040, 30) inside, 10-30 bone blobs (ellipsoids inside
-    the body) N(2000, 200); rounded and clamped to [0, vmax].  Generated per z-slab.
+    the body) N(2000, 200); rounded and clamped to [0, vmax].  Generated per z-slab;
+    each blob is evaluated only inside its bounding box.
     """
     rng = np.random.default_rng(seed)
     N, M, L = shape
@@ -83,7 +84,6 @@ def ct_phantom(shape=(512, 512, 512), seed=0, vmax=4095, slab=32):
     n_bone = int(rng.integers(10, 31))
     bones = []
     for _ in range(n_bone):
-        # centre drawn inside the body, radii small relative to it
         while True:
             c = body_c + rng.uniform(-1, 1, size=3) * body_a * 0.8
             if (((c - body_c) / body_a) ** 2).sum() <= 0.64:
@@ -91,21 +91,30 @@ def ct_phantom(shape=(512, 512, 512), seed=0, vmax=4095, slab=32):
         a = dims * rng.uniform(0.02, 0.08, size=3)
         bones.append((c, a))
     out = np.empty(shape, dtype=np.uint16)
-    yy, xx = np.meshgrid(np.arange(M, dtype=np.float64), np.arange(L, dtype=np.float64), indexing="ij")
+    yy = np.arange(M, dtype=np.float64)[:, None]
+    xx = np.arange(L, dtype=np.float64)[None, :]
     for z0 in range(0, N, slab):
         z1 = min(N, z0 + slab)
         nz = z1 - z0
         zz = np.arange(z0, z1, dtype=np.float64)[:, None, None]
         body = _ellipsoid_mask(zz, yy[None], xx[None], body_c, body_a)
-        vol = rng.integers(0, 51, size=(nz, M, L)).astype(np.float64)
-        tissue = rng.normal(1040.0, 30.0, size=(nz, M, L))
+        vol = rng.integers(0, 51, size=(nz, M, L)).astype(np.float32)
+        tissue = rng.normal(1040.0, 30.0, size=(nz, M, L)).astype(np.float32)
         vol = np.where(body, tissue, vol)
         bone_mask = np.zeros((nz, M, L), dtype=bool)
         for c, a in bones:
-            bone_mask |= _ellipsoid_mask(zz, yy[None], xx[None], c, a)
+            lo = np.maximum(np.floor(c - a), [z0, 0, 0]).astype(int)
+            hi = np.minimum(np.ceil(c + a) + 1, [z1, M, L]).astype(int)
+            if (hi <= lo).any():
+                continue
+            sub = _ellipsoid_mask(np.arange(lo[0], hi[0], dtype=np.float64)[:, None, None],
+                                  np.arange(lo[1], hi[1], dtype=np.float64)[None, :, None],
+                                  np.arange(lo[2], hi[2], dtype=np.float64)[None, None, :], c, a)
+            bone_mask[lo[0] - z0:hi[0] - z0, lo[1]:hi[1], lo[2]:hi[2]] |= sub
         bone_mask &= body
-        if bone_mask.any():
-            vol[bone_mask] = rng.normal(2000.0, 200.0, size=int(bone_mask.sum()))
+        nb = int(bone_mask.sum())
+        if nb:
+            vol[bone_mask] = rng.normal(2000.0, 200.0, size=nb)
         out[z0:z1] = np.clip(np.rint(vol), 0, vmax).astype(np.uint16)
     return out
 

@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Projection images (step 1, Section 3.1) must equal the oracle's line sums bit for bit;
+moments of orders <= 4 must equal the exact integers of eq. (2) bit for bit; every
+order's FP64 value must be the double nearest to the exact integer (so the relative
+error is <= 2^-53, inside the 1e-12 budget for orders 5-16).
+"""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.native as onative
+import synth
+from gpu_util import assert_moments_equal, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dpm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2012_08099_amd as m
+    m.lib()  # raises if the HIP library is missing
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+IMAGE_CASES = [
+    ((16, 8, 64), np.uint16, 6),     # fast path, 8-lane sub-rows
+    ((32, 5, 512), np.uint16, 6),    # fast path, full 64-lane rows
+    ((29, 7, 13), np.uint8, 6),      # generic: ragged x and z
+    ((20, 3, 1100), np.uint16, 4),   # generic: 3 column tiles, ragged
+    ((16, 4, 1024), np.uint8, 3),    # fast: 2 column tiles
+    ((24, 3, 40), np.uint16, 16),    # all three direction groups, generic
+    ((32, 2, 128), np.uint16, 16),   # all three direction groups, fast
+    ((1, 1, 1), np.uint8, 2),
+    ((5, 2, 8), np.uint8, 0),
+]
+
+
+@pytest.mark.parametrize("shape,dt,K", IMAGE_CASES)
+def test_projection_images_bit_exact(dpm, shape, dt, K):
+    say("images", shape, dt.__name__, K)
+    V = synth.uniform_volume(shape, dt, seed=hash((shape, K)) % 1000)
+    imgs = dpm.project_images(to_dev(V), K)
+    for d in range(K + 1):
+        a, b = dpm.direction(d)
+        ref = oracle.projection_image(V, a, b)
+        got = imgs[d].cpu().numpy().astype(np.int64)
+        assert got.shape == ref.shape, (d, got.shape, ref.shape)
+        assert np.array_equal(got, ref), f"image {d} ({a},{b}) differs"
+
+
+MOMENT_CASES = [
+    ((64, 64, 64), np.uint8, 3),     # the 64^3 uint8 order-3 configuration
+    ((29, 7, 13), np.uint8, 6),
+    ((33, 9, 70), np.uint16, 6),
+    ((48, 16, 64), np.uint16, 6),
+    ((16, 16, 16), np.uint16, 16),
+    ((40, 12, 24), np.uint8, 16),
+    ((1, 1, 1), np.uint16, 4),
+    ((1, 50, 1), np.uint8, 5),
+    ((17, 1, 3), np.uint16, 7),
+    ((3, 2, 600), np.uint16, 5),
+    ((32, 8, 128), np.uint16, 12),
+    ((16, 8, 64), np.uint16, 0),
+    ((16, 8, 64), np.uint8, 1),
+]
+
+
+@pytest.mark.parametrize("shape,dt,K", MOMENT_CASES)
+def test_moments_random(dpm, shape, dt, K):
+    say("moments", shape, dt.__name__, K)
+    V = synth.uniform_volume(shape, dt, seed=(shape[0] * 7 + K) % 997)
+    res = dpm.moments(to_dev(V), K)
+    assert_moments_equal(res, oracle.moments_exact(V, K), K, f"{shape} K={K}")
+
+
+def test_all_zero_volume(dpm):
+    V = np.zeros((48, 16, 64), dtype=np.uint16)
+    res = dpm.moments(to_dev(V), 6)
+    assert all(v == 0 for v in res.exact) and not res.fp64.any()
+
+
+def test_saturated_volume(dpm):
+    V = np.full((64, 32, 128), 65535, dtype=np.uint16)
+    res = dpm.moments(to_dev(V), 8)
+    assert_moments_equal(res, oracle.moments_exact(V, 8), 8, "saturated")
+
+
+@pytest.mark.parametrize("corner", [(0, 0, 0), (31, 15, 63), (0, 15, 0), (31, 0, 63), (7, 3, 40)])
+def test_impulse(dpm, corner):
+    V = np.zeros((32, 16, 64), dtype=np.uint16)
+    V[corner] = 65535
+    res = dpm.moments(to_dev(V), 10)
+    assert_moments_equal(res, oracle.moments_exact(V, 10), 10, f"impulse {corner}")
+
+
+def test_mri_phantom_256_order6(dpm):
+    say("mri 256^3 K=6")
+    V = synth.mri_phantom((256, 256, 256), seed=0)
+    res = dpm.moments(to_dev(V), 6)
+    assert_moments_equal(res, onative.moments_hoisted(V, 6), 6, "mri256")
+
+
+def test_ct_512_order6_full(dpm):
+    say("ct 512^3 K=6")
+    V = synth.ct_phantom((512, 512, 512), seed=0)
+    res = dpm.moments(to_dev(V), 6)
+    assert_moments_equal(res, onative.moments_hoisted(V, 6), 6, "ct512")
+
+
+def test_ct_128_order16_full(dpm):
+    say("ct 128^3 K=16")
+    V = synth.ct_phantom((128, 128, 128), seed=1)
+    res = dpm.moments(to_dev(V), 16)
+    assert_moments_equal(res, oracle.moments_exact(V, 16), 16, "ct128 K=16")
+
+
+def test_deterministic(dpm):
+    V = synth.mri_phantom((64, 64, 64), seed=3)
+    a = dpm.moments(to_dev(V), 9)
+    b = dpm.moments(to_dev(V), 9)
+    assert a.exact == b.exact and np.array_equal(a.fp64.view(np.uint64), b.fp64.view(np.uint64))
+
+
+def test_async_on_side_stream(dpm):
+    import torch
+    V = synth.uniform_volume((48, 24, 96), np.uint16, seed=5)
+    vol = to_dev(V)
+    K = 6
+    nm, nm4 = dpm.num_moments(K), dpm.num_moments(4)
+    ex = torch.zeros((nm4, 2), dtype=torch.int64, device="cuda:0")
+    fp = torch.zeros(nm, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(dpm.workspace_bytes(vol.shape, 2, K), dtype=torch.uint8, device="cuda:0")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    dpm.moments_async(vol, K, ex, fp, ws, stream=s)
+    s.synchronize()
+    got = dpm.Moments(K, dpm._exact_from_tensor(ex), fp.cpu().numpy())
+    assert_moments_equal(got, oracle.moments_exact(V, K), K, "async")
+
+
+def test_invalid_arguments(dpm):
+    import torch
+    lib = dpm.lib()
+    vol = torch.zeros((4, 4, 8), dtype=torch.uint8, device="cuda:0")
+    with pytest.raises((ValueError, dpm.DpmError)):
+        dpm.moments(vol, 17)
+    out = dpm._lib.Out(None, None)
+    bad = dpm._lib.Dims(0, 4, 4)
+    assert lib.dpm_moments_async(ctypes.c_void_p(vol.data_ptr()), bad, 1, 3, ctypes.byref(out), None, 0, None) == -1
+    good = dpm._lib.Dims(8, 4, 4)
+    assert lib.dpm_moments_async(ctypes.c_void_p(vol.data_ptr()), good, 9, 3, ctypes.byref(out), None, 0, None) == -1
+    # workspace smaller than required
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda:0")
+    ex = torch.zeros((20, 2), dtype=torch.int64, device="cuda:0")
+    out = dpm._lib.Out(ex.data_ptr(), None)
+    rc = lib.dpm_moments_async(ctypes.c_void_p(vol.data_ptr()), good, 1, 3, ctypes.byref(out),
+                               ctypes.c_void_p(ws.data_ptr()), 16, None)
+    assert rc == -3
+
+
+@pytest.mark.parametrize("n,seed", [(40, 0), (1000, 1)])
+def test_batched_matches_single_and_oracle(dpm, n, seed):
+    import torch
+    say("batched", n)
+    rois = synth.roi_batch(n, seed=seed)
+    K = 4
+    packed, desc = dpm.pack_rois(rois, "cuda:0")
+    nm = dpm.num_moments(K)
+    ex = torch.zeros((n * nm, 2), dtype=torch.int64, device="cuda:0")
+    fp = torch.zeros(n * nm, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(dpm.batched_workspace_bytes(desc, K), dtype=torch.uint8, device="cuda:0")
+    dpm.moments_batched(packed, desc, K, ex, fp, ws)
+    torch.cuda.synchronize()
+    exact = dpm._exact_from_tensor(ex)
+    fpn = fp.cpu().numpy()
+    for i, V in enumerate(rois):
+        ref = onative.moments_hoisted(V, K)
+        got = dpm.Moments(K, exact[i * nm:(i + 1) * nm], fpn[i * nm:(i + 1) * nm])
+        assert_moments_equal(got, ref, K, f"roi {i} {V.shape}")
+        if i < 25:
+            single = dpm.moments(to_dev(V), K)
+            assert single.exact == got.exact
