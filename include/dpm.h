@@ -140,6 +140,26 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
 /* Free every library-owned device workspace and cached plan. */
 int dpm_release(void);
 
+/* ---- stage timing (tracing) --------------------------------------------------
+ * While enabled, every dpm_moments / dpm_moments_async / dpm_moments_batched call
+ * records HIP events on its own stream before the projection kernel and after each of
+ * the four stages.  dpm_profile_collect waits for the recorded events, returns the summed
+ * device time per stage and clears the record.  Event creation happens at record
+ * time, so enable this only for measurement (it is host-side overhead, not device
+ * work).  Not thread-safe with concurrent callers on different streams. */
+typedef struct {
+    int32_t calls;
+    int32_t reserved;
+    double ms_project;    /* projection kernel(s): one pass over the volume       */
+    double ms_power;      /* exact power sums of the image rows                  */
+    double ms_reduce;     /* y-weighted reduction to 2D moments                  */
+    double ms_recombine;  /* recombination into 3D moments                       */
+    double ms_total;
+} dpm_profile;
+
+int dpm_profile_enable(int on);
+int dpm_profile_collect(dpm_profile *out);
+
 /* ---- introspection used by the host-side tests ------------------------------ */
 
 /* Exact recombination weight of Section 3.2 generalised: for total x-z degree k,

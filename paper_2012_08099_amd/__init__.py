@@ -22,7 +22,8 @@ from ._lib import DpmError, Dims, I128, Out, PlanInfo, Roi, check, lib
 __all__ = [
     "DpmError", "Moments", "moment_list", "num_moments", "moment_index", "direction", "image_width",
     "workspace_bytes", "plan", "moments", "moments_async", "project_images", "moments_batched",
-    "batched_workspace_bytes", "pack_rois", "recomb_weight", "release",
+    "batched_workspace_bytes", "pack_rois", "recomb_weight", "release", "profile_enable",
+    "profile_collect",
 ]
 
 KMAX = 16
@@ -206,6 +207,19 @@ def recomb_weight(k, p, d):
     n, den = ctypes.c_int64(), ctypes.c_uint64()
     check(lib().dpm_recomb_weight(k, p, d, ctypes.byref(n), ctypes.byref(den)), "dpm_recomb_weight")
     return n.value, den.value
+
+
+def profile_enable(on=True):
+    """Record HIP events around each stage of every following call (tracing)."""
+    check(lib().dpm_profile_enable(1 if on else 0), "dpm_profile_enable")
+
+
+def profile_collect():
+    """Wait for the recorded events; return summed per-stage device milliseconds."""
+    p = _lib.Profile()
+    check(lib().dpm_profile_collect(ctypes.byref(p)), "dpm_profile_collect")
+    return {"calls": p.calls, "ms_project": p.ms_project, "ms_power": p.ms_power, "ms_reduce": p.ms_reduce,
+            "ms_recombine": p.ms_recombine, "ms_total": p.ms_total}
 
 
 def release():

@@ -52,6 +52,12 @@ class PlanInfo(ctypes.Structure):
                 ("workspace", ctypes.c_int64)]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("calls", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms_project", ctypes.c_double),
+                ("ms_power", ctypes.c_double), ("ms_reduce", ctypes.c_double), ("ms_recombine", ctypes.c_double),
+                ("ms_total", ctypes.c_double)]
+
+
 Dims = ctypes.c_int64 * 3
 
 # exported symbol -> (restype, argtypes)
@@ -77,6 +83,8 @@ SIGNATURES = {
     "dpm_release": (ctypes.c_int, []),
     "dpm_recomb_weight": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]),
+    "dpm_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "dpm_profile_collect": (ctypes.c_int, [ctypes.POINTER(Profile)]),
     "dpm_plan": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(PlanInfo)]),
 }

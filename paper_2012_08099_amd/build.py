@@ -19,9 +19,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdpm.so")
 SOURCES = [
-    "slice_g0_u16_n4.hip", "slice_g0_u16_n8.hip", "slice_g0_u8_n4.hip", "slice_g0_u8_n8.hip",
-    "slice_g12_u16.hip", "slice_g12_u8.hip", "slice_batched.hip", "moment_kernels.hip",
-    "slice_dispatch.cpp", "dpm_api.cpp", "batched.cpp",
+    "slice_g0_u16_fast.hip", "slice_g0_u16_gen.hip", "slice_g0_u8_fast.hip", "slice_g0_u8_gen.hip",
+    "slice_g12_u16.hip", "slice_g12_u8.hip", "slice_batched.hip", "power_kernels.hip",
+    "moment_kernels.hip", "slice_dispatch.cpp", "dpm_api.cpp", "batched.cpp",
 ]
 ARCH = "gfx950"
 

@@ -18,6 +18,9 @@ namespace dpm {
 int batched_ensure_tables();  // dpm_api.cpp
 int batched_numsum_bits(int k);
 void batched_set_error(int e);
+void batched_prof_mark(int idx, hipStream_t st);
+int batched_powtab(int amax, int K, PowTab &out);
+bool batched_pow_columns(int amax, int K, int32_t colstart[KMAX + 2]);
 }  // namespace dpm
 
 namespace {
@@ -33,14 +36,15 @@ int bitlen_u64(uint64_t v) {
 }
 
 struct BPlan {
-    int K = 0, nrois = 0, items = 0, npairs = 0;
+    int K = 0, nrois = 0, items = 0, npairs = 0, ntiles = 0;
     int nls = 4, nlr = 4;
-    int jobbins = 512;
     size_t lds = 0;
     bool has_u8 = false, has_u16 = false;
+    bool mfma = false;
+    int amax = 64;
     std::vector<RoiDesc> rd;
     std::vector<BatchItem> it;
-    size_t off_rd = 0, off_it = 0, off_part = 0, off_m2 = 0, total = 0;
+    size_t off_rd = 0, off_it = 0, off_rows = 0, off_part = 0, off_m2 = 0, total = 0;
 };
 
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
@@ -51,7 +55,11 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     p.nrois = n;
     p.npairs = n_pairs(K);
     p.rd.resize(n);
+    const int nd = K + 1;
     int brec = 0, bsl = 0;
+    bool small_p = true;
+    int64_t row_base = 0;
+    int item0 = 0, tile0 = 0;
     std::vector<std::pair<int64_t, int>> order;  // (cost, roi)
     for (int i = 0; i < n; ++i) {
         const dpm_roi &r = rois[i];
@@ -60,6 +68,7 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
         if (r.dims[0] > 4096 || r.dims[1] > 4096 || r.dims[2] > 4096) return DPM_ERANGE;
         (elem == 1 ? p.has_u8 : p.has_u16) = true;
         RoiDesc &d = p.rd[i];
+        d = RoiDesc{};
         d.offset = (int64_t)r.offset_bytes;
         d.L = r.dims[0];
         d.M = r.dims[1];
@@ -87,54 +96,60 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
         for (int k = 0; k <= K; ++k)
             for (int q = 0; k + q <= K; ++q)
                 brec = std::max(brec, bvol + k * bu + q * by + batched_numsum_bits(k) + 2);
-        order.push_back({d.L * d.N, i});
-        // LDS of one item of this ROI (all items of a ROI share the geometry shape)
+        if ((double)vmax * (double)std::max(d.L, d.N) >= 268435456.0) small_p = false;
+        // geometry of this ROI's items (full z range): LDS and row layout
         ItemGeom ig;
-        item_geometry(0, K + 1 < 7 ? K + 1 : 7, d.L, d.N, 0, d.N, ig);
-        const int nj = count_jobs(ig, K + 1 < 7 ? K + 1 : 7, p.jobbins);
-        p.lds = std::max(p.lds, ((size_t)ig.lds_dwords + (size_t)nj * (KMAX + 1) * 4) * 4);
+        item_geometry(0, nd, d.L, d.N, 0, d.N, ig);
+        p.lds = std::max(p.lds, (size_t)ig.lds_dwords * 4);
+        int32_t off = 0, nsl = 0;
+        for (int sl = 0; sl < 14; ++sl) {
+            int32_t len = 0;
+            if (sl < 2 * nd && ig.seg_ahi[sl] >= ig.seg_alo[sl]) len = round64((int64_t)ig.seg_ahi[sl] + 1);
+            d.slot_off[sl] = off;
+            d.slot_len[sl] = len;
+            off += len;
+            if (len) ++nsl;
+            p.amax = std::max(p.amax, (int)len);
+        }
+        d.row_stride = off;
+        d.row_base = row_base;
+        row_base += (int64_t)off * d.M;
+        d.item0 = item0;
+        d.nitems = (int32_t)d.M;
+        item0 += (int32_t)d.M;
+        d.tile0 = tile0;
+        tile0 += nsl * (int)((d.M + 15) / 16);
+        order.push_back({d.L * d.N, i});
     }
+    p.ntiles = tile0;
     if (bsl > 128) return DPM_ERANGE;
     p.nls = 4;
     if (brec <= 128) p.nlr = 4;
     else if (brec <= 256) p.nlr = 8;
     else return DPM_ERANGE;
     if (p.lds > 160 * 1024) return DPM_ERANGE;
-    // items longest slice first; item slot = position in this order
+    int32_t cs[KMAX + 2];
+    p.mfma = small_p && p.amax <= 8192 && batched_pow_columns(p.amax, K, cs);
+    // projection work items, largest slices first (LPT order)
     std::stable_sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
-    int slot = 0;
-    std::vector<std::vector<BatchItem>> per(n);
     for (auto &o : order) {
         const int i = o.second;
         for (int64_t y = 0; y < p.rd[i].M; ++y) {
             BatchItem b{};
             b.roi = i;
-            b.slot = slot++;
+            b.slot = (int32_t)p.it.size();
             b.y = (int32_t)y;
             b.zs = 0;
             b.ze = (int32_t)p.rd[i].N;
-            per[i].push_back(b);
+            p.it.push_back(b);
         }
     }
-    // grid order = slot order; per-ROI index lists for the reduction
-    p.it.resize(slot);
-    std::vector<BatchItem> byroi;
-    byroi.reserve(slot);
-    for (int i = 0; i < n; ++i) {
-        p.rd[i].item0 = (int32_t)byroi.size();
-        p.rd[i].nitems = (int32_t)per[i].size();
-        for (auto &b : per[i]) {
-            byroi.push_back(b);
-            p.it[b.slot] = b;
-        }
-    }
-    // the grid walks p.it (slot order); the reduction walks byroi via item0/nitems
-    p.it.insert(p.it.end(), byroi.begin(), byroi.end());
-    p.items = slot;
+    p.items = (int)p.it.size();
     p.off_rd = 0;
     p.off_it = al(sizeof(RoiDesc) * n);
-    p.off_part = p.off_it + al(sizeof(BatchItem) * p.it.size());
-    p.off_m2 = p.off_part + al((size_t)p.items * p.npairs * p.nls * 4);
+    p.off_rows = p.off_it + al(sizeof(BatchItem) * p.it.size());
+    p.off_part = p.off_rows + al((size_t)row_base * 4);
+    p.off_m2 = p.off_part + al((size_t)p.items * 2 * (K + 1) * (K + 1) * p.nls * 4);
     p.total = p.off_m2 + al((size_t)n * p.npairs * (K + 1) * p.nlr * 4);
     return DPM_OK;
 }
@@ -161,8 +176,11 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
     uint8_t *ws = static_cast<uint8_t *>(workspace);
     RoiDesc *drd = reinterpret_cast<RoiDesc *>(ws + p.off_rd);
     BatchItem *dit = reinterpret_cast<BatchItem *>(ws + p.off_it);
+    int32_t *rows = reinterpret_cast<int32_t *>(ws + p.off_rows);
     uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
     uint32_t *m2 = reinterpret_cast<uint32_t *>(ws + p.off_m2);
+    PowTab pt{};
+    if (p.mfma && (rc = batched_powtab(p.amax, max_order, pt))) return rc;
     hipError_t e = hipMemcpyAsync(drd, p.rd.data(), sizeof(RoiDesc) * p.rd.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(dit, p.it.data(), sizeof(BatchItem) * p.it.size(), hipMemcpyHostToDevice, st);
@@ -173,18 +191,36 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
         return DPM_EDEVICE;
     }
     const int nd = max_order + 1;
-    BatchSliceArgs a{static_cast<const uint8_t *>(packed), drd, dit, max_order, p.jobbins, p.npairs, part};
-    if (p.has_u16) e = launch_slice_batched(2, p.nls, 0, nd, a, p.items, p.lds, st);
-    if (e == hipSuccess && p.has_u8) e = launch_slice_batched(1, p.nls, 0, nd, a, p.items, p.lds, st);
+    batched_prof_mark(0, st);
+    BatchSliceArgs a{static_cast<const uint8_t *>(packed), drd, dit, max_order, rows};
+    if (p.has_u16) e = launch_slice_batched(2, 0, nd, a, p.items, p.lds, st);
+    if (e == hipSuccess && p.has_u8) e = launch_slice_batched(1, 0, nd, a, p.items, p.lds, st);
+    if (e == hipSuccess) batched_prof_mark(1, st);
     if (e == hipSuccess) {
-        // the reduction's per-ROI item lists follow the slot-ordered grid list
-        ReduceBatchedArgs r{part, drd, dit + p.items, n_rois, max_order, p.npairs, m2};
+        PowerArgs pa{};
+        pa.rows = rows;
+        pa.rois = drd;
+        pa.nrois = n_rois;
+        pa.nitems = p.items;
+        pa.K = max_order;
+        pa.d_first = 0;
+        pa.d_last = max_order;
+        pa.ntiles = p.ntiles;
+        pa.pow = pt;
+        pa.part = part;
+        e = launch_power(p.nls, pa, st);
+    }
+    if (e == hipSuccess) batched_prof_mark(2, st);
+    if (e == hipSuccess) {
+        ReduceBatchedArgs r{part, drd, dit, n_rois, max_order, p.npairs, m2};
         e = launch_reduce_batched(p.nls, p.nlr, r, st);
     }
+    if (e == hipSuccess) batched_prof_mark(3, st);
     if (e == hipSuccess) {
         RecombArgs c{m2, n_rois, max_order, p.npairs, out_device->exact, out_device->fp64, nullptr};
         e = launch_recombine(p.nlr, c, st);
     }
+    if (e == hipSuccess) batched_prof_mark(4, st);
     if (e != hipSuccess) {
         batched_set_error((int)e);
         return DPM_EDEVICE;

@@ -8,12 +8,14 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <vector>
 
 #include "../../include/dpm.h"
 #include "dpm_common.h"
 #include "kernels.h"
+#include "mw.h"
 
 namespace {
 
@@ -63,6 +65,114 @@ int ensure_device_tables() {
     return DPM_OK;
 }
 
+// ------------------------------------------------------------------ MFMA power tables
+// Limbs (7 bits) of a^k for a in [0, amax), k <= K, laid out as the B operand of
+// v_mfma_i32_16x16x64_i8 (see PowTab).  Built once per (device, amax, K).
+struct PowKey {
+    int dev, amax, K;
+    bool operator<(const PowKey &o) const {
+        return dev != o.dev ? dev < o.dev : amax != o.amax ? amax < o.amax : K < o.K;
+    }
+};
+std::map<PowKey, PowTab> g_pow;
+
+// columns of a^k: 1 for k = 0, else ceil(bits((amax-1)^k) / 7)
+int bitlen_mw(const mw::Int<8> &v) {
+    for (int l = 7; l >= 0; --l)
+        if (v.w[l]) return 32 * l + 32 - __builtin_clz(v.w[l]);
+    return 0;
+}
+
+bool pow_columns(int amax, int K, int32_t colstart[KMAX + 2]) {
+    mw::Int<8> p;
+    mw::set_u64(p, 1);
+    int c = 0;
+    for (int k = 0; k <= K; ++k) {
+        colstart[k] = c;
+        if (k == 0) {
+            c += 1;
+        } else {
+            mw::mul_u32(p, (uint32_t)(amax - 1));
+            const int b = bitlen_mw(p);
+            c += b == 0 ? 1 : (b + 6) / 7;
+        }
+    }
+    colstart[K + 1] = c;
+    return amax <= 65536;
+}
+
+int get_powtab(int amax, int K, PowTab &out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    auto it = g_pow.find(PowKey{dev, amax, K});
+    if (it != g_pow.end()) {
+        out = it->second;
+        return DPM_OK;
+    }
+    PowTab t{};
+    if (!pow_columns(amax, K, t.colstart)) return DPM_ENOTSUP;
+    const int ncol = t.colstart[K + 1];
+    t.amax = amax;
+    t.nt = (ncol + 15) / 16;
+    const int nks = amax / 64;
+    std::vector<uint8_t> h((size_t)nks * t.nt * 64 * 16, 0);
+    std::vector<int> colk(ncol), colu(ncol);
+    for (int k = 0; k <= K; ++k)
+        for (int c = t.colstart[k]; c < t.colstart[k + 1]; ++c) {
+            colk[c] = k;
+            colu[c] = c - t.colstart[k];
+        }
+    for (int a = 0; a < amax; ++a) {
+        const int ks = a / 64, kq = (a % 64) / 16, i = a % 16;
+        mw::Int<8> pw[KMAX + 1];
+        mw::set_u64(pw[0], 1);
+        for (int k = 1; k <= K; ++k) {
+            pw[k] = pw[k - 1];
+            mw::mul_u32(pw[k], (uint32_t)a);
+        }
+        for (int col = 0; col < ncol; ++col) {
+            const int bit = 7 * colu[col];
+            const mw::Int<8> &v = pw[colk[col]];
+            const uint32_t lo = v.w[bit >> 5] >> (bit & 31);
+            const uint32_t hi = ((bit >> 5) + 1 < 8 && (bit & 31)) ? v.w[(bit >> 5) + 1] << (32 - (bit & 31)) : 0u;
+            const int tile = col / 16, lane = kq * 16 + (col % 16);
+            h[(((size_t)ks * t.nt + tile) * 64 + lane) * 16 + i] = (uint8_t)((lo | hi) & 0x7f);
+        }
+    }
+    void *d = nullptr;
+    e = hipMalloc(&d, h.size());
+    if (e != hipSuccess) {
+        g_last_hip_error = (int)e;
+        return DPM_ENOMEM;
+    }
+    e = hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+    t.b = static_cast<const uint4 *>(d);
+    g_pow[PowKey{dev, amax, K}] = t;
+    out = t;
+    return DPM_OK;
+}
+
+// ------------------------------------------------------------------ stage timing
+struct StageEvents {
+    hipEvent_t e[5];
+};
+bool g_prof_on = false;
+std::vector<StageEvents> g_prof;
+
+// Record event `idx` of the current call (creates the call's events at idx 0).
+void prof_mark(int idx, hipStream_t st) {
+    if (!g_prof_on) return;
+    if (idx == 0) {
+        StageEvents ev{};
+        for (int i = 0; i < 5; ++i) (void)hipEventCreate(&ev.e[i]);
+        g_prof.push_back(ev);
+    }
+    if (!g_prof.empty()) (void)hipEventRecord(g_prof.back().e[idx], st);
+}
+
 // ------------------------------------------------------------------ planning
 struct Plan {
     int K = 0, nd = 0, elem = 0;
@@ -77,6 +187,12 @@ struct Plan {
     int jobbins = 512;
     int npairs = 0;
     int bits_slice = 0, bits_moment = 0;
+    bool mfma = false;   // power sums on the matrix cores
+    int amax = 0;        // coordinate magnitudes covered by the power table
+    RowLayout rl{};
+    int nslots_used = 0;
+    uint64_t slot_mask = 0;
+    size_t rows_bytes = 0;
     size_t part_bytes = 0, m2_bytes = 0, ws_bytes = 0;
 };
 
@@ -169,10 +285,6 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
     p.items = (int)(p.M * p.zsplits);
     int rc = plan_widths(p);
     if (rc) return rc;
-    if (p.nd > 7) {  // the later direction groups are built with 256-bit partials only
-        p.nls = 8;
-        if (p.nlr < 8) p.nlr = 8;
-    }
     lane_layout(p.L, p.R, p.CT);
     const int64_t lanes = (p.L + G - 1) / G;
     const bool lanes_exact = (lanes == (int64_t)p.R * p.CT);
@@ -183,30 +295,58 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
         if (atoi(e)) p.fast = false;
     }
     p.npairs = n_pairs(K);
-    // groups and LDS per group (the largest item is the first; the last may differ)
+    // groups, LDS per group and the row layout (the first item is the largest; the
+    // last one may differ)
+    const int64_t firsts[2] = {0, (int64_t)(p.zsplits - 1) * p.zrows};
     p.ngroups = 0;
+    int64_t lens[NSLOT] = {};
     for (int g = 0; g < NGROUP; ++g) {
         const int b = group_begin(g), e = std::min(group_end(g), p.nd);
         if (e <= b) break;
         p.gnd[g] = e - b;
         ++p.ngroups;
         size_t best = 0;
-        const int64_t firsts[2] = {0, (int64_t)(p.zsplits - 1) * p.zrows};
         for (int s = 0; s < 2; ++s) {
             const int64_t zs0 = firsts[s], ze0 = std::min<int64_t>(zs0 + p.zrows, p.N);
             ItemGeom ig;
             item_geometry(g, p.gnd[g], p.L, p.N, zs0, ze0, ig);
-            const int nj = count_jobs(ig, p.gnd[g], p.jobbins);
-            const size_t nk = (size_t)(KMAX + 1 - b);
-            const size_t bytes = ((size_t)ig.lds_dwords + (size_t)nj * nk * p.nls) * 4;
-            best = std::max(best, bytes);
+            best = std::max(best, (size_t)ig.lds_dwords * 4);
+            for (int i = 0; i < p.gnd[g]; ++i)
+                for (int side = 0; side < 2; ++side)
+                    if (ig.seg_ahi[2 * i + side] >= ig.seg_alo[2 * i + side])
+                        lens[2 * (b + i) + side] = std::max<int64_t>(lens[2 * (b + i) + side], ig.seg_ahi[2 * i + side] + 1);
         }
         p.lds[g] = best;
         if (best > 160 * 1024) return DPM_ERANGE;
     }
-    p.part_bytes = align_up((size_t)p.items * p.npairs * p.nls * 4);
+    int64_t off = 0, amax = 64;
+    for (int sl = 0; sl < NSLOT; ++sl) {
+        const int32_t len = lens[sl] ? round64(lens[sl]) : 0;
+        p.rl.slot_off[sl] = (int32_t)off;
+        p.rl.slot_len[sl] = len;
+        if (len) {
+            ++p.nslots_used;
+            p.slot_mask |= (uint64_t)1 << sl;
+        }
+        off += len;
+        amax = std::max<int64_t>(amax, len);
+    }
+    p.rl.row_stride = off;
+    p.rows_bytes = align_up((size_t)p.items * off * 4);
+    {
+        // matrix-core power sums: row values below 2^28 (4 limbs of 7 bits)
+        const uint64_t vmax = p.elem == 1 ? 255u : 65535u;
+        const bool small_p = (double)vmax * (double)std::max<int64_t>(p.L, p.zrows) < 268435456.0;
+        int32_t cs[KMAX + 2];
+        p.mfma = small_p && amax <= 8192 && pow_columns((int)amax, p.K, cs);
+        if (const char *e = std::getenv("DPM_NO_MFMA")) {
+            if (atoi(e)) p.mfma = false;
+        }
+        p.amax = (int)amax;
+    }
+    p.part_bytes = align_up((size_t)p.items * 2 * (K + 1) * (K + 1) * p.nls * 4);
     p.m2_bytes = align_up((size_t)p.npairs * (K + 1) * p.nlr * 4);
-    p.ws_bytes = p.part_bytes + p.m2_bytes;
+    p.ws_bytes = p.rows_bytes + p.part_bytes + p.m2_bytes;
     return DPM_OK;
 }
 
@@ -240,8 +380,16 @@ int ensure_buf(void *&ptr, size_t &have, size_t need) {
 int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img_off,
              const int64_t *img_w, void *exact, double *fp64, void *ws, hipStream_t st) {
     uint8_t *base = static_cast<uint8_t *>(ws);
-    uint32_t *part = reinterpret_cast<uint32_t *>(base);
-    uint32_t *m2 = reinterpret_cast<uint32_t *>(base + p.part_bytes);
+    int32_t *rows = reinterpret_cast<int32_t *>(base);
+    uint32_t *part = reinterpret_cast<uint32_t *>(base + p.rows_bytes);
+    uint32_t *m2 = reinterpret_cast<uint32_t *>(base + p.rows_bytes + p.part_bytes);
+    PowTab pt{};
+    const bool moments = (exact || fp64);
+    if (p.mfma && moments) {
+        int prc = get_powtab(p.amax, p.K, pt);
+        if (prc) return prc;
+    }
+    if (moments) prof_mark(0, st);
     for (int g = 0; g < p.ngroups; ++g) {
         SliceArgs a{};
         a.vol = static_cast<const uint8_t *>(vol);
@@ -252,27 +400,42 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
         a.pitch_z = p.L * p.M;
         a.zsplits = p.zsplits;
         a.zrows = p.zrows;
-        a.K = p.K;
         a.R = p.R;
         a.CT = p.CT;
-        a.jobbins = p.jobbins;
-        a.npairs = p.npairs;
-        a.part = part;
+        a.rows = rows;
+        a.rl = p.rl;
         a.images = images;
         for (int i = 0; i < 7; ++i) {
             a.img_off[i] = (images && i < p.gnd[g]) ? img_off[group_begin(g) + i] : 0;
             a.img_w[i] = (images && i < p.gnd[g]) ? img_w[group_begin(g) + i] : 0;
         }
-        hipError_t e = launch_slice(p.elem, p.nls, p.fast, g, p.gnd[g], a, p.items, p.lds[g], st);
+        hipError_t e = launch_slice(p.elem, p.fast, g, p.gnd[g], a, p.items, p.lds[g], st);
         if (e != hipSuccess) return hip_fail(e);
     }
-    if (!exact && !fp64) return DPM_OK;
-    ReduceArgs r{part, p.items, p.zsplits, p.K, p.npairs, m2};
-    hipError_t e = launch_reduce(p.nls, p.nlr, r, st);
+    if (!moments) return DPM_OK;
+    PowerArgs pa{};
+    pa.rows = rows;
+    pa.rl = p.rl;
+    pa.rois = nullptr;
+    pa.nitems = p.items;
+    pa.K = p.K;
+    pa.d_first = 0;
+    pa.d_last = p.K;
+    pa.ntiles = p.nslots_used * ((p.items + 15) / 16);
+    pa.pow = pt;
+    pa.part = part;
+    prof_mark(1, st);
+    hipError_t e = launch_power(p.nls, pa, st);
     if (e != hipSuccess) return hip_fail(e);
+    prof_mark(2, st);
+    ReduceArgs r{part, p.items, p.zsplits, p.K, p.npairs, p.slot_mask, m2};
+    e = launch_reduce(p.nls, p.nlr, r, st);
+    if (e != hipSuccess) return hip_fail(e);
+    prof_mark(3, st);
     RecombArgs c{m2, 1, p.K, p.npairs, exact, fp64, nullptr};
     e = launch_recombine(p.nlr, c, st);
     if (e != hipSuccess) return hip_fail(e);
+    prof_mark(4, st);
     return DPM_OK;
 }
 
@@ -286,6 +449,12 @@ int current_device(int &dev) {
 }  // namespace
 
 namespace dpm {
+int batched_powtab(int amax, int K, PowTab &out) { return get_powtab(amax, K, out); }
+bool batched_pow_columns(int amax, int K, int32_t colstart[KMAX + 2]) { return pow_columns(amax, K, colstart); }
+void batched_prof_mark(int idx, hipStream_t st) {
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    prof_mark(idx, st);
+}
 int batched_ensure_tables() { return ensure_device_tables(); }
 int batched_numsum_bits(int k) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
@@ -440,6 +609,11 @@ int dpm_release(void) {
     int rc = DPM_OK;
     int cur = 0;
     (void)hipGetDevice(&cur);
+    for (auto &kv : g_pow) {
+        (void)hipSetDevice(kv.first.dev);
+        if (hipFree(const_cast<uint4 *>(kv.second.b)) != hipSuccess) rc = DPM_EDEVICE;
+    }
+    g_pow.clear();
     for (int d = 0; d < 64; ++d) {
         if (!g_ws[d].ptr && !g_ws[d].out) continue;
         (void)hipSetDevice(d);
@@ -448,6 +622,38 @@ int dpm_release(void) {
         g_ws[d] = DevWs{};
     }
     (void)hipSetDevice(cur);
+    return rc;
+}
+
+int dpm_profile_enable(int on) {
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    g_prof_on = on != 0;
+    return DPM_OK;
+}
+
+int dpm_profile_collect(dpm_profile *out) {
+    if (!out) return DPM_EINVAL;
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    *out = dpm_profile{};
+    int rc = DPM_OK;
+    for (auto &ev : g_prof) {
+        float t[4] = {0, 0, 0, 0}, tot = 0;
+        hipError_t e = hipEventSynchronize(ev.e[4]);
+        for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventElapsedTime(&t[i], ev.e[i], ev.e[i + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&tot, ev.e[0], ev.e[4]);
+        if (e != hipSuccess) {
+            rc = hip_fail(e);
+        } else {
+            out->calls += 1;
+            out->ms_project += t[0];
+            out->ms_power += t[1];
+            out->ms_reduce += t[2];
+            out->ms_recombine += t[3];
+            out->ms_total += tot;
+        }
+        for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev.e[i]);
+    }
+    g_prof.clear();
     return rc;
 }
 

@@ -37,11 +37,10 @@ __host__ __device__ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_
 // Voxels per lane along x: one 16-byte load (uint16) or 8-byte load (uint8).
 constexpr int G = 8;
 
-// LDS padding period of a sheared row accumulator: one pad dword per PP bins makes
-// the flush of lane windows (lane stride alpha*G bins) conflict-free.
-__host__ __device__ constexpr int dir_pp(int d) {
-    return (dir_alpha(d) == 2 && iabs_c(dir_beta(d)) != 3) ? 16 : 8;
-}
+// LDS padding period of a row accumulator: one pad dword per PP bins.  Lanes of a
+// sub-row flush windows at a stride of alpha*G bins, i.e. 9*alpha padded dwords: odd
+// (conflict-free) for alpha = 1, 3 and two-way for alpha = 2.
+__host__ __device__ constexpr int dir_pp(int d) { return 8; }
 // Rows per window block: the smallest T with beta*T = 0 mod PP, so every block base
 // is PP-aligned relative to the row origin and flush offsets are compile-time.
 __host__ __device__ constexpr int dir_td(int d) {
@@ -60,8 +59,10 @@ __host__ __device__ constexpr int dir_shift(int d) {
 constexpr int NGROUP = 3;
 __host__ __device__ constexpr int group_begin(int g) { return g == 0 ? 0 : g == 1 ? 7 : 12; }
 __host__ __device__ constexpr int group_end(int g) { return g == 0 ? 7 : g == 1 ? 12 : 17; }
-// Rows per chunk of a group = lcm of its T_d (16 for group 0, 8 otherwise).
-__host__ __device__ constexpr int group_rows(int g) { return g == 0 ? 16 : 8; }
+// Rows per chunk (unit of work and of double buffering) = lcm of the group's T_d.
+__host__ __device__ constexpr int group_rows(int g) { return 8; }
+// Copies of the (0,1) row accumulator: 8-lane groups g and g+4 of a wave share copy g % 4.
+constexpr int YZ_COPIES = 4;
 constexpr int ZALIGN = 16;  // z-split boundaries are multiples of every group's chunk
 
 __host__ __device__ constexpr int n_moments(int K) { return (K + 1) * (K + 2) * (K + 3) / 6; }
@@ -81,16 +82,21 @@ __host__ __device__ constexpr int n_pairs(int K) { return (K + 1) * (K + 2) / 2;
 constexpr int MAXSEG = 2 * 7;  // per group: <= 7 directions, each split at its origin
 
 struct DirGeom {
-    int64_t lo;      // bin of LDS index 0
-    int64_t o;       // image column of the true origin (|beta| (N-1) if beta < 0)
-    int64_t rb_lo;   // smallest bin that can hold voxels of this item
-    int64_t rb_hi;   // largest such bin
+    int32_t lo;      // bin of LDS index 0
+    int32_t o;       // image column of the true origin (|beta| (N-1) if beta < 0)
+    int32_t rb_lo;   // smallest bin that can hold voxels of this item
+    int32_t rb_hi;   // largest such bin
     int32_t lds_off; // dword offset of the row accumulator
     int32_t lds_len; // dwords (padded)
 };
 
+// Power-sum segments: each direction's row split at its origin into a negative side
+// (slot 2i, coordinate a = o - bin) and a non-negative side (slot 2i+1, a = bin - o).
+// An empty side has alo > ahi.
 struct ItemGeom {
     DirGeom dir[7];
+    int32_t seg_alo[MAXSEG];
+    int32_t seg_ahi[MAXSEG];
     int32_t yz_off;     // dword offset of the (0,1) accumulator copies
     int32_t yz_stride;  // dwords between copies (odd)
     int32_t n_chunks;   // chunks of group_rows() rows in [zs, ze)
@@ -99,78 +105,85 @@ struct ItemGeom {
 
 DPM_HD int64_t padded(int64_t u, int pp) { return u + u / pp; }
 
-// xlanes = lanes that hold voxels per row = ceil(L / G)
-DPM_HD void item_geometry(int g, int nd, int64_t L, int64_t N, int64_t zs, int64_t ze,
-                          ItemGeom &ig) {
+// Geometry of direction i of group g for rows [zs, ze) (no LDS offset yet).
+DPM_HD void dir_geometry(int g, int i, int64_t L, int64_t N, int64_t zs, int64_t ze, DirGeom &dg,
+                         int32_t &alo_neg, int32_t &ahi_neg, int32_t &alo_pos, int32_t &ahi_pos) {
     const int T = group_rows(g);
-    const int64_t xl = (L + G - 1) / G;
-    const int64_t Xp = xl * G;                 // padded x extent
+    const int64_t Xp = (L + G - 1) / G * G;    // padded x extent
     const int64_t nch = (ze - zs + T - 1) / T;
     const int64_t zlast = zs + nch * T - 1;    // last row any window may cover
+    const int d = group_begin(g) + i;
+    const int64_t a = dir_alpha(d), b = dir_beta(d);
+    const int64_t o = b < 0 ? -b * (N - 1) : 0;
+    int64_t bmin, bmax, rlo, rhi;
+    if (d == 1) {  // (0,1): bin = z
+        bmin = zs;
+        bmax = zlast;
+        rlo = zs;
+        rhi = ze - 1;
+    } else if (b >= 0) {
+        bmin = b * zs + o;
+        bmax = a * (Xp - 1) + b * zlast + o;
+        rlo = b * zs + o;
+        rhi = a * (L - 1) + b * (ze - 1) + o;
+    } else {
+        bmin = b * zlast + o;
+        bmax = a * (Xp - 1) + b * zs + o;
+        rlo = b * (ze - 1) + o;
+        rhi = a * (L - 1) + b * zs + o;
+    }
+    dg.o = (int32_t)o;
+    dg.lo = (int32_t)bmin;
+    dg.rb_lo = (int32_t)rlo;
+    dg.rb_hi = (int32_t)rhi;
+    dg.lds_len = d == 1 ? (int32_t)(YZ_COPIES * ((nch * T) | 1)) : (int32_t)(padded(bmax - bmin, dir_pp(d)) + 1);
+    // sides: negative [rlo, min(rhi, o-1)], non-negative [max(rlo, o), rhi]
+    const int64_t n1 = rhi < o - 1 ? rhi : o - 1;
+    const int64_t p0 = rlo > o ? rlo : o;
+    alo_neg = (int32_t)(o - n1);
+    ahi_neg = (int32_t)(o - rlo);
+    if (n1 < rlo) {
+        alo_neg = 1;
+        ahi_neg = 0;
+    }
+    alo_pos = (int32_t)(p0 - o);
+    ahi_pos = (int32_t)(rhi - o);
+    if (rhi < p0) {
+        alo_pos = 1;
+        ahi_pos = 0;
+    }
+}
+
+// Whole-item geometry (host, and device for batched items).
+DPM_HD void item_geometry(int g, int nd, int64_t L, int64_t N, int64_t zs, int64_t ze, ItemGeom &ig) {
+    const int T = group_rows(g);
+    const int64_t nch = (ze - zs + T - 1) / T;
     int32_t off = 0;
     ig.n_chunks = (int32_t)nch;
     ig.yz_off = -1;
     ig.yz_stride = 0;
-    for (int i = 0; i < nd; ++i) {
-        const int d = group_begin(g) + i;
-        const int64_t a = dir_alpha(d), b = dir_beta(d);
-        DirGeom &dg = ig.dir[i];
-        dg.o = b < 0 ? -b * (N - 1) : 0;
-        if (d == 1) {  // (0,1): bin = z; 8 copies, one per 8-lane group of a wave
-            dg.lo = zs;
-            dg.rb_lo = zs;
-            dg.rb_hi = ze - 1;
-            int32_t stride = (int32_t)(nch * T) | 1;
-            ig.yz_off = off;
-            ig.yz_stride = stride;
-            dg.lds_off = off;
-            dg.lds_len = 8 * stride;
-            off += dg.lds_len;
+    for (int i = 0; i < 7; ++i) {
+        if (i >= nd) {
+            ig.seg_alo[2 * i] = ig.seg_alo[2 * i + 1] = 1;
+            ig.seg_ahi[2 * i] = ig.seg_ahi[2 * i + 1] = 0;
             continue;
         }
-        int64_t bmin, bmax;
-        if (b >= 0) {
-            bmin = b * zs + dg.o;
-            bmax = a * (Xp - 1) + b * zlast + dg.o;
-            dg.rb_lo = b * zs + dg.o;
-            dg.rb_hi = a * (L - 1) + b * (ze - 1) + dg.o;
-        } else {
-            bmin = b * zlast + dg.o;
-            bmax = a * (Xp - 1) + b * zs + dg.o;
-            dg.rb_lo = b * (ze - 1) + dg.o;
-            dg.rb_hi = a * (L - 1) + b * zs + dg.o;
-        }
-        dg.lo = bmin;
-        const int pp = dir_pp(d);
+        DirGeom &dg = ig.dir[i];
+        dir_geometry(g, i, L, N, zs, ze, dg, ig.seg_alo[2 * i], ig.seg_ahi[2 * i], ig.seg_alo[2 * i + 1],
+                     ig.seg_ahi[2 * i + 1]);
         dg.lds_off = off;
-        dg.lds_len = (int32_t)(padded(bmax - bmin, pp) + 1);
+        if (group_begin(g) + i == 1) {
+            ig.yz_off = off;
+            ig.yz_stride = dg.lds_len / YZ_COPIES;
+        }
         off += dg.lds_len;
     }
     ig.lds_dwords = off;
 }
 
-// Power-sum jobs: each direction's real bin range split at its origin into a
-// negative side (coordinate a = o - b) and a non-negative side (a = b - o), each cut
-// into pieces of at most `jobbins` bins.
-DPM_HD bool seg_range(const DirGeom &dg, int side, int64_t &b0, int64_t &b1) {
-    if (side == 0) {
-        b0 = dg.rb_lo;
-        b1 = dg.rb_hi < dg.o - 1 ? dg.rb_hi : dg.o - 1;
-    } else {
-        b0 = dg.rb_lo > dg.o ? dg.rb_lo : dg.o;
-        b1 = dg.rb_hi;
-    }
-    return b1 >= b0;
-}
-
-DPM_HD int count_jobs(const ItemGeom &ig, int nd, int jobbins) {
-    int n = 0;
-    for (int i = 0; i < nd; ++i)
-        for (int side = 0; side < 2; ++side) {
-            int64_t b0, b1;
-            if (seg_range(ig.dir[i], side, b0, b1)) n += (int)((b1 - b0 + jobbins) / jobbins);
-        }
-    return n;
-}
+// Row storage of the power-sum input: segment slot s of every item holds `len` int32
+// values for a = 0 .. len-1 (zero outside the item's [alo, ahi]); len is a multiple of
+// 64 and equal for all items of a launch.
+DPM_HD int32_t round64(int64_t v) { return (int32_t)((v + 63) / 64 * 64); }
 
 }  // namespace dpm

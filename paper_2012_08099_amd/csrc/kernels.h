@@ -10,16 +10,37 @@ namespace dpm {
 constexpr int SLICE_WAVES = 4;  // waves per projection workgroup
 constexpr int NLR_MAX = 12;     // widest 2D-moment / recombination integer (32-bit limbs)
 
+// Exact power sums on the matrix cores: the row values P(a) and the powers a^k are
+// split into 7-bit limbs (int8 MFMA operands, int32 accumulation, all exact), and
+// R_k = sum_a a^k P(a) is reassembled from the limb-pair sums.  `b` holds the powers'
+// limbs already in the B-operand layout of v_mfma_i32_16x16x64_i8:
+// b[(ks * nt + tile) * 64 + lane] = 16 bytes, byte i = limb column (16 tile + lane % 16)
+// of a = 64 ks + 16 (lane / 16) + i.
+struct PowTab {
+    const uint4 *b;                 // null: use the VALU power sums
+    int32_t amax;                   // a in [0, amax); multiple of 64
+    int32_t nt;                     // 16-column tiles
+    int32_t colstart[KMAX + 2];     // first limb column of a^k; colstart[K+1] = columns
+};
+
+// Image rows handed from the projection kernel to the power-sum kernel: item i, slot
+// s = 2 d + side holds slot_len[s] int32 values (a = 0 .. len-1) at
+// rows[i * row_stride + slot_off[s]].
+constexpr int NSLOT = 2 * NDIR_MAX;
+struct RowLayout {
+    int32_t slot_off[NSLOT];
+    int32_t slot_len[NSLOT];   // multiple of 64; 0 = empty slot
+    int64_t row_stride;        // int32 values per item
+};
+
 struct SliceArgs {
     const uint8_t *vol;
     int64_t L, M, N;
     int64_t pitch_y, pitch_z;  // elements
     int32_t zsplits, zrows;
-    int32_t K;
     int32_t R, CT;             // lanes per sub-row, column tiles
-    int32_t jobbins;
-    int32_t npairs;            // pairs (d, k) over all groups
-    uint32_t *part;            // [item][npairs][NLS]
+    int32_t *rows;             // [item][row_stride]
+    RowLayout rl;
     int32_t *images;           // optional
     int64_t img_off[7];        // element offset of each image of the group
     int64_t img_w[7];          // widths
@@ -30,8 +51,13 @@ struct RoiDesc {
     int64_t L, M, N;
     int32_t elem;              // bytes per voxel
     int32_t R, CT;
-    int32_t item0;             // first work item of this ROI
+    int32_t item0;             // first work item (= first row block) of this ROI
     int32_t nitems;
+    int32_t tile0;             // first power-sum tile of this ROI
+    int64_t row_base;          // int32 offset of item0's rows
+    int32_t row_stride;        // int32 values per item
+    int32_t slot_off[14];      // orders <= 6: slots 0..13
+    int32_t slot_len[14];
 };
 
 struct BatchItem {
@@ -45,21 +71,35 @@ struct BatchSliceArgs {
     const RoiDesc *rois;
     const BatchItem *items;
     int32_t K;
-    int32_t jobbins;
-    int32_t npairs;
-    uint32_t *part;
+    int32_t *rows;
 };
 
-hipError_t launch_slice(int elem, int nls, bool fast, int g, int nd, const SliceArgs &a, int items,
-                        size_t lds, hipStream_t st);
-hipError_t launch_slice_batched(int elem, int nls, int g, int nd, const BatchSliceArgs &a, int items,
-                                size_t lds, hipStream_t st);
+// Power sums of the image rows: part[item][slot][k][NLS] = sum_a a^k row(a), exact.
+struct PowerArgs {
+    const int32_t *rows;
+    RowLayout rl;               // single volume
+    const RoiDesc *rois;        // batched (null for a single volume)
+    int32_t nrois;
+    int32_t nitems;
+    int32_t K;
+    int32_t d_first, d_last;    // slots of directions [d_first, d_last] (inclusive)
+    int32_t ntiles;             // work tiles (16 items x one slot)
+    PowTab pow;                 // null b: VALU path
+    uint32_t *part;
+};
+hipError_t launch_power(int nls, const PowerArgs &a, hipStream_t st);
 
-// y-weighted reduction: M2[pair][q] = sum_items y^q part[item][pair]
+hipError_t launch_slice(int elem, bool fast, int g, int nd, const SliceArgs &a, int items, size_t lds,
+                        hipStream_t st);
+hipError_t launch_slice_batched(int elem, int g, int nd, const BatchSliceArgs &a, int items, size_t lds,
+                                hipStream_t st);
+
+// y-weighted reduction: M2[pair][q] = sum_items y^q (r_pos + (-1)^k r_neg)
 struct ReduceArgs {
-    const uint32_t *part;
+    const uint32_t *part;      // [item][slot][k][NLS]
     int32_t nitems, zsplits;
     int32_t K, npairs;
+    uint64_t slot_mask;        // bit s: slot s holds data
     uint32_t *m2;              // [pair][K+1][NLR]
 };
 hipError_t launch_reduce(int nls, int nlr, const ReduceArgs &a, hipStream_t st);

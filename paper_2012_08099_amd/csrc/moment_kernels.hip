@@ -68,6 +68,21 @@ __device__ mw::Int<NLR> load_part(const uint32_t *p) {
     return mw::resize<NLR, NLS>(v);
 }
 
+// x-z power sum of image d at degree k for one item: non-negative side plus (-1)^k
+// times the negative side (a = o - bin).
+template <int NLS, int NLR>
+__device__ mw::Int<NLR> row_sum(const uint32_t *item_part, int K, int d, int k, uint64_t mask) {
+    mw::Int<NLR> v;
+    mw::set_zero(v);
+    if ((mask >> (2 * d + 1)) & 1u) v = load_part<NLS, NLR>(item_part + ((size_t)(2 * d + 1) * (K + 1) + k) * NLS);
+    if ((mask >> (2 * d)) & 1u) {
+        const mw::Int<NLR> n = load_part<NLS, NLR>(item_part + ((size_t)(2 * d) * (K + 1) + k) * NLS);
+        if (k & 1) mw::sub(v, n);
+        else mw::add(v, n);
+    }
+    return v;
+}
+
 // grid: one block per (pair, q) triple
 template <int NLS, int NLR>
 __global__ void __launch_bounds__(RED_THREADS) reduce_kernel(ReduceArgs a) {
@@ -76,9 +91,10 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_kernel(ReduceArgs a) {
     decode_triple(a.K, blockIdx.x, pair, d, k, q);
     mw::Int<NLR> acc;
     mw::set_zero(acc);
+    const size_t istride = (size_t)2 * (a.K + 1) * (a.K + 1) * NLS;
     for (int i = threadIdx.x; i < a.nitems; i += blockDim.x) {
         const uint32_t y = (uint32_t)(i / a.zsplits);
-        mw::Int<NLR> v = load_part<NLS, NLR>(a.part + ((size_t)i * a.npairs + pair) * NLS);
+        mw::Int<NLR> v = row_sum<NLS, NLR>(a.part + i * istride, a.K, d, k, a.slot_mask);
         for (int j = 0; j < q; ++j) mw::mul_u32(v, y);
         mw::add(acc, v);
     }
@@ -90,7 +106,10 @@ template <int NLS, int NLR>
 __global__ void __launch_bounds__(RED_THREADS) reduce_batched_kernel(ReduceBatchedArgs a) {
     __shared__ uint32_t red[RED_THREADS * NLR];
     const RoiDesc rd = a.rois[blockIdx.x];
-    const int ntri = n_moments(a.K) - 0;  // upper bound; loop stops by decode
+    uint64_t mask = 0;
+    for (int s = 0; s < 14; ++s)
+        if (rd.slot_len[s]) mask |= (uint64_t)1 << s;
+    const size_t istride = (size_t)2 * (a.K + 1) * (a.K + 1) * NLS;
     int t = 0;
     for (int dd = 0; dd <= a.K; ++dd)
         for (int kk = dd; kk <= a.K; ++kk)
@@ -99,15 +118,14 @@ __global__ void __launch_bounds__(RED_THREADS) reduce_batched_kernel(ReduceBatch
                 mw::Int<NLR> acc;
                 mw::set_zero(acc);
                 for (int i = threadIdx.x; i < rd.nitems; i += blockDim.x) {
-                    const BatchItem it = a.items[rd.item0 + i];
-                    mw::Int<NLR> v = load_part<NLS, NLR>(a.part + ((size_t)it.slot * a.npairs + pair) * NLS);
-                    for (int j = 0; j < qq; ++j) mw::mul_u32(v, (uint32_t)it.y);
+                    mw::Int<NLR> v = row_sum<NLS, NLR>(a.part + (size_t)(rd.item0 + i) * istride, a.K, dd, kk, mask);
+                    for (int j = 0; j < qq; ++j) mw::mul_u32(v, (uint32_t)i);
                     mw::add(acc, v);
                 }
                 block_reduce_store<NLR>(
                     acc, a.m2 + (((size_t)blockIdx.x * a.npairs + pair) * (a.K + 1) + qq) * NLR, red);
             }
-    (void)ntri;
+    (void)t;
 }
 
 // decode graded index m -> (p, q, r)

@@ -1,29 +1,25 @@
-// Dispatch of the projection kernel instantiations by dtype, group and width.
+// Dispatch of the projection kernel instantiations by dtype, group and load path.
 #include "kernels.h"
 
 namespace dpm {
-#define DECL(name) \
-    hipError_t name(bool fast, int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st);
-DECL(launch_slice_g0_u16_n4)
-DECL(launch_slice_g0_u16_n8)
-DECL(launch_slice_g0_u8_n4)
-DECL(launch_slice_g0_u8_n8)
+#define DECL(name) hipError_t name(int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st);
+DECL(launch_slice_g0_u16_fast)
+DECL(launch_slice_g0_u16_gen)
+DECL(launch_slice_g0_u8_fast)
+DECL(launch_slice_g0_u8_gen)
 #undef DECL
 hipError_t launch_slice_g12_u16(int g, bool fast, int nd, const SliceArgs &a, int items, size_t lds,
                                 hipStream_t st);
 hipError_t launch_slice_g12_u8(int g, bool fast, int nd, const SliceArgs &a, int items, size_t lds,
                                hipStream_t st);
 
-hipError_t launch_slice(int elem, int nls, bool fast, int g, int nd, const SliceArgs &a, int items,
-                        size_t lds, hipStream_t st) {
-    if (nls != 4 && nls != 8) return hipErrorInvalidValue;
+hipError_t launch_slice(int elem, bool fast, int g, int nd, const SliceArgs &a, int items, size_t lds,
+                        hipStream_t st) {
     if (g == 0) {
-        if (elem == 2) return nls == 4 ? launch_slice_g0_u16_n4(fast, nd, a, items, lds, st)
-                                       : launch_slice_g0_u16_n8(fast, nd, a, items, lds, st);
-        return nls == 4 ? launch_slice_g0_u8_n4(fast, nd, a, items, lds, st)
-                        : launch_slice_g0_u8_n8(fast, nd, a, items, lds, st);
+        if (elem == 2) return fast ? launch_slice_g0_u16_fast(nd, a, items, lds, st)
+                                   : launch_slice_g0_u16_gen(nd, a, items, lds, st);
+        return fast ? launch_slice_g0_u8_fast(nd, a, items, lds, st) : launch_slice_g0_u8_gen(nd, a, items, lds, st);
     }
-    if (nls != 8) return hipErrorInvalidValue;  // orders >= 7 always use 256-bit partials
     return elem == 2 ? launch_slice_g12_u16(g, fast, nd, a, items, lds, st)
                      : launch_slice_g12_u8(g, fast, nd, a, items, lds, st);
 }

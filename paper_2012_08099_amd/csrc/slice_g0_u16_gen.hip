@@ -1,0 +1,9 @@
+// Instantiations of the projection kernel (split across files for parallel builds).
+#include "slice_impl.h"
+
+namespace dpm {
+
+hipError_t launch_slice_g0_u16_gen(int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st) {
+    return launch_nd<uint16_t, 0, false>(nd, a, items, lds, st);
+}
+}  // namespace dpm
