@@ -181,8 +181,7 @@ def main(argv=None):
                                f"({nm} moments; orders<=4 exact int128, all FP64)", "volumes_rotated": a.nvol},
         "hbm_gbs_algorithmic": voxels * elem / (ms_step / 1e3) / 1e9,
         "stages_ms": {"project": proj_ms, "power": prof["ms_power"] / max(prof["calls"], 1),
-                      "reduce": prof["ms_reduce"] / max(prof["calls"], 1),
-                      "recombine": prof["ms_recombine"] / max(prof["calls"], 1)},
+                      "combine": prof["ms_combine"] / max(prof["calls"], 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "slice_kernel (projection, one pass over the volume)",

@@ -143,7 +143,7 @@ int dpm_release(void);
 /* ---- stage timing (tracing) --------------------------------------------------
  * While enabled, every dpm_moments / dpm_moments_async / dpm_moments_batched call
  * records HIP events on its own stream before the projection kernel and after each of
- * the four stages.  dpm_profile_collect waits for the recorded events, returns the summed
+ * the three stages.  dpm_profile_collect waits for the recorded events, returns the summed
  * device time per stage and clears the record.  Event creation happens at record
  * time, so enable this only for measurement (it is host-side overhead, not device
  * work).  Not thread-safe with concurrent callers on different streams. */
@@ -151,9 +151,8 @@ typedef struct {
     int32_t calls;
     int32_t reserved;
     double ms_project;    /* projection kernel(s): one pass over the volume       */
-    double ms_power;      /* exact power sums of the image rows                  */
-    double ms_reduce;     /* y-weighted reduction to 2D moments                  */
-    double ms_recombine;  /* recombination into 3D moments                       */
+    double ms_power;      /* exact power sums of the image rows, y-weighted per tile */
+    double ms_combine;    /* tile sums to 2D moments and recombination into 3D   */
     double ms_total;
 } dpm_profile;
 

@@ -218,8 +218,8 @@ def profile_collect():
     """Wait for the recorded events; return summed per-stage device milliseconds."""
     p = _lib.Profile()
     check(lib().dpm_profile_collect(ctypes.byref(p)), "dpm_profile_collect")
-    return {"calls": p.calls, "ms_project": p.ms_project, "ms_power": p.ms_power, "ms_reduce": p.ms_reduce,
-            "ms_recombine": p.ms_recombine, "ms_total": p.ms_total}
+    return {"calls": p.calls, "ms_project": p.ms_project, "ms_power": p.ms_power,
+            "ms_combine": p.ms_combine, "ms_total": p.ms_total}
 
 
 def release():

@@ -54,7 +54,7 @@ class PlanInfo(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms_project", ctypes.c_double),
-                ("ms_power", ctypes.c_double), ("ms_reduce", ctypes.c_double), ("ms_recombine", ctypes.c_double),
+                ("ms_power", ctypes.c_double), ("ms_combine", ctypes.c_double),
                 ("ms_total", ctypes.c_double)]
 
 

@@ -1,6 +1,6 @@
 // Batched regions of interest: many independent volumes of uneven size in one
-// launch sequence (projection kernel over every (ROI, y-slice) work item, one
-// reduction block per ROI, one recombination block per ROI).  Work items are laid out
+// launch sequence (projection kernel over every (ROI, y-slice) work item, power-sum
+// tiles of every ROI in one grid, one recombination wave per (ROI, moment)).  Work items are laid out
 // longest-first (LPT order) so the large ROIs start early and the small ones fill the
 // tail of the grid.
 #include <hip/hip_runtime.h>
@@ -44,7 +44,7 @@ struct BPlan {
     int amax = 64;
     std::vector<RoiDesc> rd;
     std::vector<BatchItem> it;
-    size_t off_rd = 0, off_it = 0, off_rows = 0, off_part = 0, off_m2 = 0, total = 0;
+    size_t off_rd = 0, off_it = 0, off_rows = 0, off_part = 0, total = 0;
 };
 
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
@@ -149,8 +149,7 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     p.off_it = al(sizeof(RoiDesc) * n);
     p.off_rows = p.off_it + al(sizeof(BatchItem) * p.it.size());
     p.off_part = p.off_rows + al((size_t)row_base * 4);
-    p.off_m2 = p.off_part + al((size_t)p.items * 2 * (K + 1) * (K + 1) * p.nls * 4);
-    p.total = p.off_m2 + al((size_t)n * p.npairs * (K + 1) * p.nlr * 4);
+    p.total = p.off_part + al((size_t)p.ntiles * (K + 1) * (K + 1) * p.nlr * 4);
     return DPM_OK;
 }
 
@@ -178,7 +177,6 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
     BatchItem *dit = reinterpret_cast<BatchItem *>(ws + p.off_it);
     int32_t *rows = reinterpret_cast<int32_t *>(ws + p.off_rows);
     uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
-    uint32_t *m2 = reinterpret_cast<uint32_t *>(ws + p.off_m2);
     PowTab pt{};
     if (p.mfma && (rc = batched_powtab(p.amax, max_order, pt))) return rc;
     hipError_t e = hipMemcpyAsync(drd, p.rd.data(), sizeof(RoiDesc) * p.rd.size(), hipMemcpyHostToDevice, st);
@@ -202,25 +200,25 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
         pa.rois = drd;
         pa.nrois = n_rois;
         pa.nitems = p.items;
+        pa.zsplits = 1;
         pa.K = max_order;
-        pa.d_first = 0;
-        pa.d_last = max_order;
         pa.ntiles = p.ntiles;
         pa.pow = pt;
         pa.part = part;
-        e = launch_power(p.nls, pa, st);
+        e = launch_power(p.nls, p.nlr, pa, st);
     }
     if (e == hipSuccess) batched_prof_mark(2, st);
     if (e == hipSuccess) {
-        ReduceBatchedArgs r{part, drd, dit, n_rois, max_order, p.npairs, m2};
-        e = launch_reduce_batched(p.nls, p.nlr, r, st);
+        FinishArgs f{};
+        f.part = part;
+        f.rois = drd;
+        f.nvol = n_rois;
+        f.K = max_order;
+        f.exact = out_device->exact;
+        f.fp64 = out_device->fp64;
+        e = launch_finish(p.nlr, f, st);
     }
     if (e == hipSuccess) batched_prof_mark(3, st);
-    if (e == hipSuccess) {
-        RecombArgs c{m2, n_rois, max_order, p.npairs, out_device->exact, out_device->fp64, nullptr};
-        e = launch_recombine(p.nlr, c, st);
-    }
-    if (e == hipSuccess) batched_prof_mark(4, st);
     if (e != hipSuccess) {
         batched_set_error((int)e);
         return DPM_EDEVICE;

@@ -156,8 +156,9 @@ int get_powtab(int amax, int K, PowTab &out) {
 }
 
 // ------------------------------------------------------------------ stage timing
+constexpr int NPROF = 4;  // start, after projection, after power sums, end
 struct StageEvents {
-    hipEvent_t e[5];
+    hipEvent_t e[NPROF];
 };
 bool g_prof_on = false;
 std::vector<StageEvents> g_prof;
@@ -167,7 +168,7 @@ void prof_mark(int idx, hipStream_t st) {
     if (!g_prof_on) return;
     if (idx == 0) {
         StageEvents ev{};
-        for (int i = 0; i < 5; ++i) (void)hipEventCreate(&ev.e[i]);
+        for (int i = 0; i < NPROF; ++i) (void)hipEventCreate(&ev.e[i]);
         g_prof.push_back(ev);
     }
     if (!g_prof.empty()) (void)hipEventRecord(g_prof.back().e[idx], st);
@@ -193,7 +194,8 @@ struct Plan {
     int nslots_used = 0;
     uint64_t slot_mask = 0;
     size_t rows_bytes = 0;
-    size_t part_bytes = 0, m2_bytes = 0, ws_bytes = 0;
+    int ntiles = 0;       // power-sum tiles: non-empty slots x ceil(items / 16)
+    size_t part_bytes = 0, ws_bytes = 0;
 };
 
 constexpr size_t kAlign = 256;
@@ -344,9 +346,9 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
         }
         p.amax = (int)amax;
     }
-    p.part_bytes = align_up((size_t)p.items * 2 * (K + 1) * (K + 1) * p.nls * 4);
-    p.m2_bytes = align_up((size_t)p.npairs * (K + 1) * p.nlr * 4);
-    p.ws_bytes = p.rows_bytes + p.part_bytes + p.m2_bytes;
+    p.ntiles = p.nslots_used * ((p.items + 15) / 16);
+    p.part_bytes = align_up((size_t)p.ntiles * (K + 1) * (K + 1) * p.nlr * 4);
+    p.ws_bytes = p.rows_bytes + p.part_bytes;
     return DPM_OK;
 }
 
@@ -382,7 +384,6 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
     uint8_t *base = static_cast<uint8_t *>(ws);
     int32_t *rows = reinterpret_cast<int32_t *>(base);
     uint32_t *part = reinterpret_cast<uint32_t *>(base + p.rows_bytes);
-    uint32_t *m2 = reinterpret_cast<uint32_t *>(base + p.rows_bytes + p.part_bytes);
     PowTab pt{};
     const bool moments = (exact || fp64);
     if (p.mfma && moments) {
@@ -418,24 +419,27 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
     pa.rl = p.rl;
     pa.rois = nullptr;
     pa.nitems = p.items;
+    pa.zsplits = p.zsplits;
     pa.K = p.K;
-    pa.d_first = 0;
-    pa.d_last = p.K;
-    pa.ntiles = p.nslots_used * ((p.items + 15) / 16);
+    pa.ntiles = p.ntiles;
     pa.pow = pt;
     pa.part = part;
     prof_mark(1, st);
-    hipError_t e = launch_power(p.nls, pa, st);
+    hipError_t e = launch_power(p.nls, p.nlr, pa, st);
     if (e != hipSuccess) return hip_fail(e);
     prof_mark(2, st);
-    ReduceArgs r{part, p.items, p.zsplits, p.K, p.npairs, p.slot_mask, m2};
-    e = launch_reduce(p.nls, p.nlr, r, st);
+    FinishArgs f{};
+    f.part = part;
+    f.rois = nullptr;
+    f.nvol = 1;
+    f.K = p.K;
+    f.slot_mask = p.slot_mask;
+    f.ipt = (p.items + 15) / 16;
+    f.exact = exact;
+    f.fp64 = fp64;
+    e = launch_finish(p.nlr, f, st);
     if (e != hipSuccess) return hip_fail(e);
     prof_mark(3, st);
-    RecombArgs c{m2, 1, p.K, p.npairs, exact, fp64, nullptr};
-    e = launch_recombine(p.nlr, c, st);
-    if (e != hipSuccess) return hip_fail(e);
-    prof_mark(4, st);
     return DPM_OK;
 }
 
@@ -637,21 +641,20 @@ int dpm_profile_collect(dpm_profile *out) {
     *out = dpm_profile{};
     int rc = DPM_OK;
     for (auto &ev : g_prof) {
-        float t[4] = {0, 0, 0, 0}, tot = 0;
-        hipError_t e = hipEventSynchronize(ev.e[4]);
-        for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventElapsedTime(&t[i], ev.e[i], ev.e[i + 1]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&tot, ev.e[0], ev.e[4]);
+        float t[NPROF - 1] = {}, tot = 0;
+        hipError_t e = hipEventSynchronize(ev.e[NPROF - 1]);
+        for (int i = 0; i + 1 < NPROF && e == hipSuccess; ++i) e = hipEventElapsedTime(&t[i], ev.e[i], ev.e[i + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&tot, ev.e[0], ev.e[NPROF - 1]);
         if (e != hipSuccess) {
             rc = hip_fail(e);
         } else {
             out->calls += 1;
             out->ms_project += t[0];
             out->ms_power += t[1];
-            out->ms_reduce += t[2];
-            out->ms_recombine += t[3];
+            out->ms_combine += t[2];
             out->ms_total += tot;
         }
-        for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev.e[i]);
+        for (int i = 0; i < NPROF; ++i) (void)hipEventDestroy(ev.e[i]);
     }
     g_prof.clear();
     return rc;

@@ -74,55 +74,39 @@ struct BatchSliceArgs {
     int32_t *rows;
 };
 
-// Power sums of the image rows: part[item][slot][k][NLS] = sum_a a^k row(a), exact.
+// Power sums of the image rows, weighted in y per tile of 16 items:
+// part[tile][k][q][NLR] = sum_{items i of the tile} y_i^q sum_a a^k row(i, slot, a), exact.
+// Tiles are numbered slot-major over the non-empty slots (batched: from RoiDesc::tile0).
 struct PowerArgs {
     const int32_t *rows;
     RowLayout rl;               // single volume
     const RoiDesc *rois;        // batched (null for a single volume)
     int32_t nrois;
     int32_t nitems;
+    int32_t zsplits;            // single volume: y of item i is i / zsplits
     int32_t K;
-    int32_t d_first, d_last;    // slots of directions [d_first, d_last] (inclusive)
     int32_t ntiles;             // work tiles (16 items x one slot)
     PowTab pow;                 // null b: VALU path
     uint32_t *part;
 };
-hipError_t launch_power(int nls, const PowerArgs &a, hipStream_t st);
+hipError_t launch_power(int nls, int nlr, const PowerArgs &a, hipStream_t st);
 
 hipError_t launch_slice(int elem, bool fast, int g, int nd, const SliceArgs &a, int items, size_t lds,
                         hipStream_t st);
 hipError_t launch_slice_batched(int elem, int g, int nd, const BatchSliceArgs &a, int items, size_t lds,
                                 hipStream_t st);
 
-// y-weighted reduction: M2[pair][q] = sum_items y^q (r_pos + (-1)^k r_neg)
-struct ReduceArgs {
-    const uint32_t *part;      // [item][slot][k][NLS]
-    int32_t nitems, zsplits;
-    int32_t K, npairs;
-    uint64_t slot_mask;        // bit s: slot s holds data
-    uint32_t *m2;              // [pair][K+1][NLR]
-};
-hipError_t launch_reduce(int nls, int nlr, const ReduceArgs &a, hipStream_t st);
-
-// batched: one block per ROI
-struct ReduceBatchedArgs {
-    const uint32_t *part;
-    const RoiDesc *rois;
-    const BatchItem *items;
-    int32_t nrois, K, npairs;
-    uint32_t *m2;              // [roi][pair][K+1][NLR]
-};
-hipError_t launch_reduce_batched(int nls, int nlr, const ReduceBatchedArgs &a, hipStream_t st);
-
-// recombination into 3D moments; grid = number of volumes
-struct RecombArgs {
-    const uint32_t *m2;        // [vol][pair][K+1][NLR]
-    int32_t nvol, K, npairs;
+// Tile sums and recombination into the 3D moments; grid = (moments, volumes).
+struct FinishArgs {
+    const uint32_t *part;      // tile partials (PowerArgs::part)
+    const RoiDesc *rois;       // batched (null for a single volume)
+    int32_t nvol, K;
+    uint64_t slot_mask;        // single volume: bit s = slot s holds data
+    int32_t ipt;               // single volume: tiles per slot
     void *exact;               // dpm_i128 [vol][n_moments(min(K,4))] or null
     double *fp64;              // [vol][n_moments(K)] or null
-    uint32_t *wide;            // optional exact values [vol][n_moments(K)][NLR]
 };
-hipError_t launch_recombine(int nlr, const RecombArgs &a, hipStream_t st);
+hipError_t launch_finish(int nlr, const FinishArgs &a, hipStream_t st);
 
 // recombination tables (host side generation, device upload)
 struct RecombTables {

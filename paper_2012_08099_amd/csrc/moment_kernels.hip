@@ -1,15 +1,17 @@
-// Second and third stages of the method, in exact multiword integers:
+// Last stage of the method, in exact multiword integers, one wave per 3D moment:
 //
-//  * reduce:    M^d_{k,q} = sum_y y^q r_{d,k}(y)  -- the y part of the 2D moments of
-//               eq. (1) for every image d, from the per-slice row power sums.
-//  * recombine: the 3D moments of Section 3.2.  For each x-z degree k and y power q,
-//               the images d = 0..k satisfy
-//                   M^d_{k,q} = sum_p C(k,p) alpha_d^p beta_d^(k-p) M_{p,q,k-p},
-//               a (k+1)x(k+1) system with exact rational inverse (Lagrange form,
-//               tables built on the host).  For k <= 4 this is eqs. (10)-(16): e.g.
-//               k = 2 gives eq. (13) and k = 3 the corrected eqs. (15)/(16).
-//               Every moment comes out as an exact integer: numerator / denominator
-//               with an exact division (shift + multiply by the odd inverse).
+//  * the 2D moments M^d_{k,q} = sum_y y^q r_{d,k}(y) of every image d (eq. 1) are the
+//    sums of the power-sum tiles of the image's two slots, the negative side taken with
+//    the sign (-1)^k (its coordinates are -a);
+//  * recombination (Section 3.2): for each x-z degree k and y power q the images
+//    d = 0..k satisfy
+//        M^d_{k,q} = sum_p C(k,p) alpha_d^p beta_d^(k-p) M_{p,q,k-p},
+//    a (k+1)x(k+1) system with exact rational inverse (Lagrange form, tables built on
+//    the host).  For k <= 4 this is eqs. (10)-(16): e.g. k = 2 gives eq. (13) and k = 3
+//    the corrected eqs. (15)/(16).
+//  The wave forms numerator = sum_d num[k][p][d] M^d_{k,q} directly from the tiles, and
+//  the moment is numerator / denominator by an exact division (shift + multiply by the
+//  odd part's inverse).
 #include "dpm_common.h"
 #include "kernels.h"
 #include "mw.h"
@@ -19,114 +21,6 @@ namespace dpm {
 __constant__ int64_t c_num[KMAX + 1][KMAX + 1][KMAX + 1];
 __constant__ int32_t c_shift[KMAX + 1][KMAX + 1];
 __constant__ uint32_t c_inv[KMAX + 1][KMAX + 1][NLR_MAX];
-
-constexpr int RED_THREADS = 256;
-
-// decode triple t (pairs in pair order, q = 0..K-k) -> (pair, k, q)
-__device__ __forceinline__ void decode_triple(int K, int t, int &pair, int &d, int &k, int &q) {
-    pair = 0;
-    for (d = 0; d <= K; ++d)
-        for (k = d; k <= K; ++k, ++pair) {
-            const int nq = K - k + 1;
-            if (t < nq) {
-                q = t;
-                return;
-            }
-            t -= nq;
-        }
-}
-
-template <int NLR>
-__device__ void block_reduce_store(mw::Int<NLR> acc, uint32_t *dst, uint32_t *red) {
-    const int tid = threadIdx.x;
-#pragma unroll
-    for (int l = 0; l < NLR; ++l) red[tid * NLR + l] = acc.w[l];
-    __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            mw::Int<NLR> a, b;
-#pragma unroll
-            for (int l = 0; l < NLR; ++l) {
-                a.w[l] = red[tid * NLR + l];
-                b.w[l] = red[(tid + s) * NLR + l];
-            }
-            mw::add(a, b);
-#pragma unroll
-            for (int l = 0; l < NLR; ++l) red[tid * NLR + l] = a.w[l];
-        }
-        __syncthreads();
-    }
-    if (tid < NLR) dst[tid] = red[tid];
-    __syncthreads();
-}
-
-template <int NLS, int NLR>
-__device__ mw::Int<NLR> load_part(const uint32_t *p) {
-    mw::Int<NLS> v;
-#pragma unroll
-    for (int l = 0; l < NLS; ++l) v.w[l] = p[l];
-    return mw::resize<NLR, NLS>(v);
-}
-
-// x-z power sum of image d at degree k for one item: non-negative side plus (-1)^k
-// times the negative side (a = o - bin).
-template <int NLS, int NLR>
-__device__ mw::Int<NLR> row_sum(const uint32_t *item_part, int K, int d, int k, uint64_t mask) {
-    mw::Int<NLR> v;
-    mw::set_zero(v);
-    if ((mask >> (2 * d + 1)) & 1u) v = load_part<NLS, NLR>(item_part + ((size_t)(2 * d + 1) * (K + 1) + k) * NLS);
-    if ((mask >> (2 * d)) & 1u) {
-        const mw::Int<NLR> n = load_part<NLS, NLR>(item_part + ((size_t)(2 * d) * (K + 1) + k) * NLS);
-        if (k & 1) mw::sub(v, n);
-        else mw::add(v, n);
-    }
-    return v;
-}
-
-// grid: one block per (pair, q) triple
-template <int NLS, int NLR>
-__global__ void __launch_bounds__(RED_THREADS) reduce_kernel(ReduceArgs a) {
-    __shared__ uint32_t red[RED_THREADS * NLR];
-    int pair, d, k, q;
-    decode_triple(a.K, blockIdx.x, pair, d, k, q);
-    mw::Int<NLR> acc;
-    mw::set_zero(acc);
-    const size_t istride = (size_t)2 * (a.K + 1) * (a.K + 1) * NLS;
-    for (int i = threadIdx.x; i < a.nitems; i += blockDim.x) {
-        const uint32_t y = (uint32_t)(i / a.zsplits);
-        mw::Int<NLR> v = row_sum<NLS, NLR>(a.part + i * istride, a.K, d, k, a.slot_mask);
-        for (int j = 0; j < q; ++j) mw::mul_u32(v, y);
-        mw::add(acc, v);
-    }
-    block_reduce_store<NLR>(acc, a.m2 + ((size_t)pair * (a.K + 1) + q) * NLR, red);
-}
-
-// grid: one block per ROI; every (pair, q) triple in turn
-template <int NLS, int NLR>
-__global__ void __launch_bounds__(RED_THREADS) reduce_batched_kernel(ReduceBatchedArgs a) {
-    __shared__ uint32_t red[RED_THREADS * NLR];
-    const RoiDesc rd = a.rois[blockIdx.x];
-    uint64_t mask = 0;
-    for (int s = 0; s < 14; ++s)
-        if (rd.slot_len[s]) mask |= (uint64_t)1 << s;
-    const size_t istride = (size_t)2 * (a.K + 1) * (a.K + 1) * NLS;
-    int t = 0;
-    for (int dd = 0; dd <= a.K; ++dd)
-        for (int kk = dd; kk <= a.K; ++kk)
-            for (int qq = 0; qq <= a.K - kk; ++qq, ++t) {
-                const int pair = pair_index(a.K, dd, kk);
-                mw::Int<NLR> acc;
-                mw::set_zero(acc);
-                for (int i = threadIdx.x; i < rd.nitems; i += blockDim.x) {
-                    mw::Int<NLR> v = row_sum<NLS, NLR>(a.part + (size_t)(rd.item0 + i) * istride, a.K, dd, kk, mask);
-                    for (int j = 0; j < qq; ++j) mw::mul_u32(v, (uint32_t)i);
-                    mw::add(acc, v);
-                }
-                block_reduce_store<NLR>(
-                    acc, a.m2 + (((size_t)blockIdx.x * a.npairs + pair) * (a.K + 1) + qq) * NLR, red);
-            }
-    (void)t;
-}
 
 // decode graded index m -> (p, q, r)
 __device__ __forceinline__ void decode_moment(int m, int &p, int &q, int &r) {
@@ -144,87 +38,68 @@ __device__ __forceinline__ void decode_moment(int m, int &p, int &q, int &r) {
 }
 
 template <int NLR>
-__global__ void __launch_bounds__(RED_THREADS) recombine_kernel(RecombArgs a) {
-    const int vol = blockIdx.x;
+__global__ void __launch_bounds__(64) finish_kernel(FinishArgs a) {
+    const int m = blockIdx.x, vol = blockIdx.y, lane = threadIdx.x;
     const int K = a.K;
-    const int nm = n_moments(K);
-    const int nm4 = n_moments(K < 4 ? K : 4);
-    const uint32_t *m2 = a.m2 + (size_t)vol * a.npairs * (K + 1) * NLR;
-    for (int m = threadIdx.x; m < nm; m += blockDim.x) {
-        int p, q, r;
-        decode_moment(m, p, q, r);
-        const int k = p + r;
-        mw::Int<NLR> num;
-        mw::set_zero(num);
-        for (int d = 0; d <= k; ++d) {
-            const int64_t c = c_num[k][p][d];
-            if (c == 0) continue;
-            mw::Int<NLR> v;
-            const uint32_t *src = m2 + ((size_t)pair_index(K, d, k) * (K + 1) + q) * NLR;
+    int p, q, r;
+    decode_moment(m, p, q, r);
+    const int k = p + r;
+    uint64_t mask = a.slot_mask;
+    int ipt = a.ipt, tile0 = 0;
+    if (a.rois) {
+        const RoiDesc &rd = a.rois[vol];
+        mask = 0;
+        for (int s = 0; s < 14 && s < 2 * (K + 1); ++s)
+            if (rd.slot_len[s]) mask |= (uint64_t)1 << s;
+        ipt = (int)((rd.M + 15) / 16);
+        tile0 = rd.tile0;
+    }
+    mw::Int<NLR> num;
+    mw::set_zero(num);
+    const int per_d = 2 * ipt;
+    for (int e = lane; e < (k + 1) * per_d; e += 64) {
+        const int d = e / per_d, rem = e - d * per_d;
+        const int side = rem / ipt, it = rem - side * ipt;
+        const int s = 2 * d + side;
+        int64_t c = c_num[k][p][d];
+        if (c == 0 || !((mask >> s) & 1u)) continue;
+        if (side == 0 && (k & 1)) c = -c;
+        const int rank = __popcll(mask & (((uint64_t)1 << s) - 1u));
+        const size_t tile = (size_t)tile0 + (size_t)rank * ipt + it;
+        const uint32_t *src = a.part + ((tile * (K + 1) + k) * (K + 1) + q) * NLR;
+        mw::Int<NLR> v;
 #pragma unroll
-            for (int l = 0; l < NLR; ++l) v.w[l] = src[l];
-            mw::Int<NLR> t = mw::mul_i64(v, c);
-            mw::add(num, t);
-        }
-        // exact division by den = 2^shift * odd
-        mw::sar(num, c_shift[k][p]);
-        mw::Int<NLR> inv;
+        for (int l = 0; l < NLR; ++l) v.w[l] = src[l];
+        mw::add(num, mw::mul_i64(v, c));
+    }
 #pragma unroll
-        for (int l = 0; l < NLR; ++l) inv.w[l] = c_inv[k][p][l];
-        const mw::Int<NLR> val = mw::mul_mod(num, inv);
-        if (a.fp64) a.fp64[(size_t)vol * nm + m] = mw::to_double(val);
-        if (a.exact && m < nm4) {
-            uint64_t *e = reinterpret_cast<uint64_t *>(a.exact) + 2 * ((size_t)vol * nm4 + m);
-            e[0] = (uint64_t)val.w[0] | ((uint64_t)val.w[1] << 32);
-            e[1] = (uint64_t)val.w[2] | ((uint64_t)val.w[3] << 32);
-        }
-        if (a.wide) {
-            uint32_t *w = a.wide + ((size_t)vol * nm + m) * NLR;
+    for (int sh = 1; sh < 64; sh <<= 1) {
+        mw::Int<NLR> o;
 #pragma unroll
-            for (int l = 0; l < NLR; ++l) w[l] = val.w[l];
-        }
+        for (int l = 0; l < NLR; ++l) o.w[l] = (uint32_t)__shfl_xor((int)num.w[l], sh, 64);
+        mw::add(num, o);
+    }
+    if (lane != 0) return;
+    // exact division by den = 2^shift * odd
+    mw::sar(num, c_shift[k][p]);
+    mw::Int<NLR> inv;
+#pragma unroll
+    for (int l = 0; l < NLR; ++l) inv.w[l] = c_inv[k][p][l];
+    const mw::Int<NLR> val = mw::mul_mod(num, inv);
+    const int nm = n_moments(K), nm4 = n_moments(K < 4 ? K : 4);
+    if (a.fp64) a.fp64[(size_t)vol * nm + m] = mw::to_double(val);
+    if (a.exact && m < nm4) {
+        uint64_t *e = reinterpret_cast<uint64_t *>(a.exact) + 2 * ((size_t)vol * nm4 + m);
+        e[0] = (uint64_t)val.w[0] | ((uint64_t)val.w[1] << 32);
+        e[1] = (uint64_t)val.w[2] | ((uint64_t)val.w[3] << 32);
     }
 }
 
-// ------------------------------------------------------------ launchers
-static int n_triples(int K) {
-    int t = 0;
-    for (int d = 0; d <= K; ++d)
-        for (int k = d; k <= K; ++k) t += K - k + 1;
-    return t;
-}
-
-template <int NLS, int NLR>
-static hipError_t red_go(const ReduceArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((reduce_kernel<NLS, NLR>), dim3(n_triples(a.K)), dim3(RED_THREADS), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce(int nls, int nlr, const ReduceArgs &a, hipStream_t st) {
-    if (nls == 4 && nlr == 4) return red_go<4, 4>(a, st);
-    if (nls == 4 && nlr == 8) return red_go<4, 8>(a, st);
-    if (nls == 4 && nlr == 12) return red_go<4, 12>(a, st);
-    if (nls == 8 && nlr == 8) return red_go<8, 8>(a, st);
-    if (nls == 8 && nlr == 12) return red_go<8, 12>(a, st);
-    return hipErrorInvalidValue;
-}
-
-template <int NLS, int NLR>
-static hipError_t redb_go(const ReduceBatchedArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL((reduce_batched_kernel<NLS, NLR>), dim3(a.nrois), dim3(RED_THREADS), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce_batched(int nls, int nlr, const ReduceBatchedArgs &a, hipStream_t st) {
-    if (nls == 4 && nlr == 4) return redb_go<4, 4>(a, st);
-    if (nls == 4 && nlr == 8) return redb_go<4, 8>(a, st);
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_recombine(int nlr, const RecombArgs &a, hipStream_t st) {
-    if (nlr == 4) hipLaunchKernelGGL((recombine_kernel<4>), dim3(a.nvol), dim3(RED_THREADS), 0, st, a);
-    else if (nlr == 8) hipLaunchKernelGGL((recombine_kernel<8>), dim3(a.nvol), dim3(RED_THREADS), 0, st, a);
-    else if (nlr == 12) hipLaunchKernelGGL((recombine_kernel<12>), dim3(a.nvol), dim3(RED_THREADS), 0, st, a);
+hipError_t launch_finish(int nlr, const FinishArgs &a, hipStream_t st) {
+    const dim3 grid(n_moments(a.K), a.nvol);
+    if (nlr == 4) hipLaunchKernelGGL((finish_kernel<4>), grid, dim3(64), 0, st, a);
+    else if (nlr == 8) hipLaunchKernelGGL((finish_kernel<8>), grid, dim3(64), 0, st, a);
+    else if (nlr == 12) hipLaunchKernelGGL((finish_kernel<12>), grid, dim3(64), 0, st, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -1,16 +1,19 @@
-// Power sums of the image rows written by the projection kernel:
+// Power sums of the image rows written by the projection kernel, weighted in y:
 //
-//     part[item][slot][k] = sum_a a^k row(item, slot, a),   d <= k <= K,  slot = 2d + side,
+//     r(item, slot, k)   = sum_a a^k row(item, slot, a),        d <= k <= K,  slot = 2d + side
+//     T(tile, k, q)      = sum_{items i of the tile} y_i^q r(i, slot, k),   q <= K - k
 //
-// exact, in multiword integers.  These are the x-z parts of the 2D moments (eq. 1) of
-// each image row about the image's true origin (Section 3.2; the negative side enters
-// the y reduction with the sign (-1)^k).
+// exact, in multiword integers.  r is the x-z part of the 2D moments (eq. 1) of one
+// image row about the image's true origin (Section 3.2; the negative side enters with
+// the sign (-1)^k later); T is a tile's share of the y part, so the 2D moment of
+// image d is the sum of T over the tiles of its two slots.
 //
-// Matrix-core path: a wave takes 16 items of one slot.  With a the contraction index,
-// the 16 rows (items) are the A operand and the limbs of a^k (precomputed table) the B
-// operand of v_mfma_i32_16x16x64_i8.  Row values (< 2^28) and powers are split into
-// 7-bit limbs, so every product and the int32 accumulation over a are exact; the 4 x L
-// limb-pair sums are reassembled into the exact sum with shifts.
+// A tile is 16 items (consecutive image rows) of one slot, one workgroup.
+// Matrix-core path: with a the contraction index, the 16 rows are the A operand and the
+// limbs of a^k (precomputed table) the B operand of v_mfma_i32_16x16x64_i8.  Row values
+// (< 2^28) and powers are split into 7-bit limbs, so every product and the int32
+// accumulation over a are exact; the four waves split the contraction, and the limb-pair
+// sums are reassembled into the exact r with shifts.
 // VALU path (row values >= 2^28): multiword products and an exact lane reduction.
 #include "dpm_common.h"
 #include "kernels.h"
@@ -26,14 +29,15 @@ struct TileInfo {
     int32_t len;        // values per row (multiple of 64)
     int64_t stride;     // int32 values between consecutive items' rows
     const int32_t *base;  // row of the tile's first item, this slot
-    int64_t pidx0;      // part index of the tile's first item
+    int32_t ybase;      // y of item i of the tile: (ybase + i) / ydiv
+    int32_t ydiv;
 };
 
 __device__ bool decode_tile(const PowerArgs &a, int tile, TileInfo &ti) {
     if (!a.rois) {
         const int ipt = (a.nitems + 15) / 16;
         int cnt = 0;
-        for (int s = 2 * a.d_first; s <= 2 * a.d_last + 1; ++s) {
+        for (int s = 0; s <= 2 * a.K + 1; ++s) {
             if (a.rl.slot_len[s] == 0) continue;
             if (tile < cnt + ipt) {
                 const int item0 = (tile - cnt) * 16;
@@ -42,7 +46,8 @@ __device__ bool decode_tile(const PowerArgs &a, int tile, TileInfo &ti) {
                 ti.len = a.rl.slot_len[s];
                 ti.stride = a.rl.row_stride;
                 ti.base = a.rows + (int64_t)item0 * a.rl.row_stride + a.rl.slot_off[s];
-                ti.pidx0 = item0;
+                ti.ybase = item0;
+                ti.ydiv = a.zsplits;
                 return true;
             }
             cnt += ipt;
@@ -67,7 +72,8 @@ __device__ bool decode_tile(const PowerArgs &a, int tile, TileInfo &ti) {
             ti.len = rd.slot_len[s];
             ti.stride = rd.row_stride;
             ti.base = a.rows + rd.row_base + (int64_t)item0 * rd.row_stride + rd.slot_off[s];
-            ti.pidx0 = rd.item0 + item0;
+            ti.ybase = item0;
+            ti.ydiv = 1;
             return true;
         }
         cnt += ipt;
@@ -92,10 +98,35 @@ __device__ __forceinline__ void add_shifted(mw::Int<N> &acc, uint32_t v, int shi
     }
 }
 
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// Epilogue shared by both paths.  Thread t holds R[j] = r(item t % 16, slot, k) for
+// k = d + t / 16 + 16 j; the 16 lanes of one k are one aligned lane group.  For every
+// q <= K - k the group sums y^q R exactly and its first lane stores T(tile, k, q).
+template <int NLS, int NLR, int NJ>
+__device__ __forceinline__ void yweight_store(const PowerArgs &a, const TileInfo &ti, int tile, int d,
+                                              const mw::Int<NLS> (&R)[NJ]) {
+    const int tid = threadIdx.x, ei = tid & 15, K = a.K;
+    const uint32_t y = (uint32_t)((ti.ybase + ei) / ti.ydiv);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int k = d + (tid >> 4) + 16 * j;
+        if (k > K) break;  // uniform over the lane group
+        mw::Int<NLR> v = mw::resize<NLR, NLS>(R[j]);  // r >= 0
+        uint32_t *dst = a.part + ((size_t)tile * (K + 1) + k) * (K + 1) * NLR;
+        for (int q = 0; q <= K - k; ++q) {
+            mw::Int<NLR> s = v;
+#pragma unroll
+            for (int m = 1; m < 16; m <<= 1) {
+                mw::Int<NLR> o;
+#pragma unroll
+                for (int l = 0; l < NLR; ++l) o.w[l] = (uint32_t)__shfl_xor((int)s.w[l], m, 64);
+                mw::add(s, o);
+            }
+            if (ei == 0)
+#pragma unroll
+                for (int l = 0; l < NLR; ++l) dst[(size_t)q * NLR + l] = s.w[l];
+            mw::mul_u32(v, y);
+        }
+    }
 }
 
 // One workgroup per tile (16 items x one slot).  The four waves split the K-steps of
@@ -103,7 +134,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // reassembles one (item, k) sum.
 constexpr int PW_NTP = 4;  // 16-column tiles per pass (4 P-limbs x 4 tiles x 4 = 64 VGPRs)
 
-template <int NLS>
+template <int NLS, int NLR>
 __global__ void __launch_bounds__(PW_WAVES * 64) power_mfma_kernel(PowerArgs a) {
     typedef int v4i __attribute__((ext_vector_type(4)));
     __shared__ int32_t ctab[4][PW_NTP][256];
@@ -145,14 +176,17 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_mfma_kernel(PowerArgs a) 
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int tp = 0; tp < PW_NTP; ++tp) acc[c][tp] = v4i{0, 0, 0, 0};
-        uint4 cur[4], nxt[4];
-        load_rows(wave, cur);
-        for (int ks = wave; ks < nks; ks += PW_WAVES) {
-            load_rows(ks + PW_WAVES, nxt);  // next K-step of this wave in flight
-            uint4 bq[PW_NTP];
+        auto load_b = [&](int ks, uint4 (&q)[PW_NTP]) {
 #pragma unroll
             for (int tp = 0; tp < PW_NTP; ++tp)
-                if (t0 + tp < nt) bq[tp] = bt[((size_t)ks * nt + t0 + tp) * 64];
+                q[tp] = (ks < nks && t0 + tp < nt) ? bt[((size_t)ks * nt + t0 + tp) * 64] : make_uint4(0u, 0u, 0u, 0u);
+        };
+        uint4 cur[4], nxt[4], bq[PW_NTP], bn[PW_NTP];
+        load_rows(wave, cur);
+        load_b(wave, bq);
+        for (int ks = wave; ks < nks; ks += PW_WAVES) {
+            load_rows(ks + PW_WAVES, nxt);  // next K-step of this wave in flight
+            load_b(ks + PW_WAVES, bn);
             const uint32_t v[16] = {cur[0].x, cur[0].y, cur[0].z, cur[0].w, cur[1].x, cur[1].y, cur[1].z, cur[1].w,
                                     cur[2].x, cur[2].y, cur[2].z, cur[2].w, cur[3].x, cur[3].y, cur[3].z, cur[3].w};
             v4i A[4];
@@ -176,6 +210,8 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_mfma_kernel(PowerArgs a) 
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) cur[i] = nxt[i];
+#pragma unroll
+            for (int tp = 0; tp < PW_NTP; ++tp) bq[tp] = bn[tp];
         }
         // partial limb-pair sums of the four waves -> ctab[c][tile][item][col]
 #pragma unroll
@@ -207,28 +243,20 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_mfma_kernel(PowerArgs a) 
         }
         __syncthreads();
     }
-    if (ei >= ti.nitems) return;
-    const int nslot = 2 * (K + 1);
-    uint32_t *dst = a.part + (((size_t)(ti.pidx0 + ei) * nslot + ti.slot) * (K + 1)) * NLS;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const int k = d + (tid >> 4) + 16 * j;
-        if (k > K) break;
-#pragma unroll
-        for (int l = 0; l < NLS; ++l) dst[(size_t)k * NLS + l] = R[j].w[l];
-    }
+    yweight_store<NLS, NLR, NJ>(a, ti, blockIdx.x, d, R);
 }
 
-template <int NLS>
+template <int NLS, int NLR>
 __global__ void __launch_bounds__(PW_WAVES * 64) power_valu_kernel(PowerArgs a) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int tile = blockIdx.x * PW_WAVES + wave;
+    __shared__ uint32_t rbuf[16][KMAX + 1][NLS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     TileInfo ti;
-    if (tile >= a.ntiles || !decode_tile(a, tile, ti)) return;
+    if (!decode_tile(a, blockIdx.x, ti)) return;  // uniform over the workgroup
     const int K = a.K;
     const int d = ti.slot >> 1;
-    const int nslot = 2 * (K + 1);
-    for (int il = 0; il < ti.nitems; ++il) {
+    for (int i = tid; i < 16 * (KMAX + 1) * NLS; i += PW_WAVES * 64) (&rbuf[0][0][0])[i] = 0u;
+    __syncthreads();
+    for (int il = wave; il < ti.nitems; il += PW_WAVES) {
         const int32_t *rp = ti.base + (int64_t)il * ti.stride;
         mw::Int<NLS> acc[KMAX + 1];
 #pragma unroll
@@ -246,7 +274,6 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_valu_kernel(PowerArgs a) 
                 }
             }
         }
-        uint32_t *dst = a.part + (((size_t)(ti.pidx0 + il) * nslot + ti.slot) * (K + 1)) * NLS;
 #pragma unroll
         for (int k = 0; k <= KMAX; ++k) {
             if (k >= d && k <= K) {
@@ -260,27 +287,36 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_valu_kernel(PowerArgs a) 
                 }
                 if (lane == 0)
 #pragma unroll
-                    for (int l = 0; l < NLS; ++l) dst[(size_t)k * NLS + l] = v.w[l];
+                    for (int l = 0; l < NLS; ++l) rbuf[il][k][l] = v.w[l];
             }
         }
     }
+    __syncthreads();
+    constexpr int NJ = (KMAX + 16) / 16;
+    mw::Int<NLS> R[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int k = d + (tid >> 4) + 16 * j;
+#pragma unroll
+        for (int l = 0; l < NLS; ++l) R[j].w[l] = k <= K ? rbuf[tid & 15][k][l] : 0u;
+    }
+    yweight_store<NLS, NLR, NJ>(a, ti, blockIdx.x, d, R);
 }
 
-template <int NLS>
+template <int NLS, int NLR>
 static hipError_t power_go(const PowerArgs &a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
-    if (a.pow.b) {
-        hipLaunchKernelGGL((power_mfma_kernel<NLS>), dim3(a.ntiles), dim3(PW_WAVES * 64), 0, st, a);
-    } else {
-        const int blocks = (a.ntiles + PW_WAVES - 1) / PW_WAVES;
-        hipLaunchKernelGGL((power_valu_kernel<NLS>), dim3(blocks), dim3(PW_WAVES * 64), 0, st, a);
-    }
+    if (a.pow.b) hipLaunchKernelGGL((power_mfma_kernel<NLS, NLR>), dim3(a.ntiles), dim3(PW_WAVES * 64), 0, st, a);
+    else hipLaunchKernelGGL((power_valu_kernel<NLS, NLR>), dim3(a.ntiles), dim3(PW_WAVES * 64), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_power(int nls, const PowerArgs &a, hipStream_t st) {
-    if (nls == 4) return power_go<4>(a, st);
-    if (nls == 8) return power_go<8>(a, st);
+hipError_t launch_power(int nls, int nlr, const PowerArgs &a, hipStream_t st) {
+    if (nls == 4 && nlr == 4) return power_go<4, 4>(a, st);
+    if (nls == 4 && nlr == 8) return power_go<4, 8>(a, st);
+    if (nls == 4 && nlr == 12) return power_go<4, 12>(a, st);
+    if (nls == 8 && nlr == 8) return power_go<8, 8>(a, st);
+    if (nls == 8 && nlr == 12) return power_go<8, 12>(a, st);
     return hipErrorInvalidValue;
 }
 

@@ -84,6 +84,26 @@ def test_moments_random(dpm, shape, dt, K):
     assert_moments_equal(res, oracle.moments_exact(V, K), K, f"{shape} K={K}")
 
 
+PATH_OVERRIDES = [
+    ({"DPM_NO_MFMA": "1"}, (33, 9, 70), np.uint16, 6),      # VALU power sums
+    ({"DPM_NO_MFMA": "1"}, (20, 6, 24), np.uint8, 16),      # VALU, every direction group
+    ({"DPM_ZSPLITS": "3"}, (48, 10, 64), np.uint16, 7),     # z-split work items
+    ({"DPM_ZSPLITS": "4", "DPM_NO_MFMA": "1"}, (70, 5, 64), np.uint8, 5),
+    ({"DPM_FORCE_GENERIC": "1"}, (32, 8, 128), np.uint16, 6),
+]
+
+
+@pytest.mark.parametrize("env,shape,dt,K", PATH_OVERRIDES)
+def test_moments_forced_paths(dpm, monkeypatch, env, shape, dt, K):
+    """The planner's alternative paths, forced through its environment overrides."""
+    say("forced", env, shape, dt.__name__, K)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    V = synth.uniform_volume(shape, dt, seed=K * 31 + shape[0])
+    res = dpm.moments(to_dev(V), K)
+    assert_moments_equal(res, oracle.moments_exact(V, K), K, f"{env} {shape} K={K}")
+
+
 def test_all_zero_volume(dpm):
     V = np.zeros((48, 16, 64), dtype=np.uint16)
     res = dpm.moments(to_dev(V), 6)
