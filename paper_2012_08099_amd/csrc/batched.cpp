@@ -1,6 +1,6 @@
 // Batched regions of interest: many independent volumes of uneven size in one
 // launch sequence (projection kernel over every (ROI, y-slice) work item, power-sum
-// tiles of every ROI in one grid, one recombination wave per (ROI, moment)).  Work items are laid out
+// tiles of every ROI in one grid, one recombination workgroup per (ROI, moment)).  Work items are laid out
 // longest-first (LPT order) so the large ROIs start early and the small ones fill the
 // tail of the grid.
 #include <hip/hip_runtime.h>

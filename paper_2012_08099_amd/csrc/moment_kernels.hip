@@ -1,4 +1,4 @@
-// Last stage of the method, in exact multiword integers, one wave per 3D moment:
+// Last stage of the method, in exact multiword integers, one workgroup per 3D moment:
 //
 //  * the 2D moments M^d_{k,q} = sum_y y^q r_{d,k}(y) of every image d (eq. 1) are the
 //    sums of the power-sum tiles of the image's two slots, the negative side taken with
@@ -9,7 +9,7 @@
 //    a (k+1)x(k+1) system with exact rational inverse (Lagrange form, tables built on
 //    the host).  For k <= 4 this is eqs. (10)-(16): e.g. k = 2 gives eq. (13) and k = 3
 //    the corrected eqs. (15)/(16).
-//  The wave forms numerator = sum_d num[k][p][d] M^d_{k,q} directly from the tiles, and
+//  The workgroup forms numerator = sum_d num[k][p][d] M^d_{k,q} directly from the tiles, and
 //  the moment is numerator / denominator by an exact division (shift + multiply by the
 //  odd part's inverse).
 #include "dpm_common.h"
@@ -37,9 +37,13 @@ __device__ __forceinline__ void decode_moment(int m, int &p, int &q, int &r) {
     r = n - p - q;
 }
 
+constexpr int FIN_THREADS = 256;
+constexpr int FIN_BATCH = 4;  // entries whose loads are in flight together
+
 template <int NLR>
-__global__ void __launch_bounds__(64) finish_kernel(FinishArgs a) {
-    const int m = blockIdx.x, vol = blockIdx.y, lane = threadIdx.x;
+__global__ void __launch_bounds__(FIN_THREADS) finish_kernel(FinishArgs a) {
+    __shared__ uint32_t wsum[FIN_THREADS / 64][NLR];
+    const int m = blockIdx.x, vol = blockIdx.y, tid = threadIdx.x;
     const int K = a.K;
     int p, q, r;
     decode_moment(m, p, q, r);
@@ -56,21 +60,30 @@ __global__ void __launch_bounds__(64) finish_kernel(FinishArgs a) {
     }
     mw::Int<NLR> num;
     mw::set_zero(num);
-    const int per_d = 2 * ipt;
-    for (int e = lane; e < (k + 1) * per_d; e += 64) {
-        const int d = e / per_d, rem = e - d * per_d;
-        const int side = rem / ipt, it = rem - side * ipt;
-        const int s = 2 * d + side;
-        int64_t c = c_num[k][p][d];
-        if (c == 0 || !((mask >> s) & 1u)) continue;
-        if (side == 0 && (k & 1)) c = -c;
-        const int rank = __popcll(mask & (((uint64_t)1 << s) - 1u));
-        const size_t tile = (size_t)tile0 + (size_t)rank * ipt + it;
-        const uint32_t *src = a.part + ((tile * (K + 1) + k) * (K + 1) + q) * NLR;
-        mw::Int<NLR> v;
+    const int per_d = 2 * ipt, nent = (k + 1) * per_d;
+    for (int e0 = tid; e0 < nent; e0 += FIN_BATCH * FIN_THREADS) {
+        mw::Int<NLR> v[FIN_BATCH];
+        int64_t c[FIN_BATCH];
+        // all loads of the batch first (coefficient and tile value are independent)
 #pragma unroll
-        for (int l = 0; l < NLR; ++l) v.w[l] = src[l];
-        mw::add(num, mw::mul_i64(v, c));
+        for (int b = 0; b < FIN_BATCH; ++b) {
+            const int e = e0 + b * FIN_THREADS;
+            const int d = e / per_d, rem = e - d * per_d;
+            const int side = rem / ipt, it = rem - side * ipt;
+            const int s = 2 * d + side;
+            mw::set_zero(v[b]);
+            c[b] = 0;
+            if (e < nent && ((mask >> s) & 1u)) {
+                c[b] = (side == 0 && (k & 1)) ? -c_num[k][p][d] : c_num[k][p][d];
+                const int rank = __popcll(mask & (((uint64_t)1 << s) - 1u));
+                const size_t tile = (size_t)tile0 + (size_t)rank * ipt + it;
+                const uint32_t *src = a.part + ((tile * (K + 1) + k) * (K + 1) + q) * NLR;
+#pragma unroll
+                for (int l = 0; l < NLR; ++l) v[b].w[l] = src[l];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < FIN_BATCH; ++b) mw::add(num, mw::mul_i64(v[b], c[b]));
     }
 #pragma unroll
     for (int sh = 1; sh < 64; sh <<= 1) {
@@ -79,7 +92,17 @@ __global__ void __launch_bounds__(64) finish_kernel(FinishArgs a) {
         for (int l = 0; l < NLR; ++l) o.w[l] = (uint32_t)__shfl_xor((int)num.w[l], sh, 64);
         mw::add(num, o);
     }
-    if (lane != 0) return;
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int l = 0; l < NLR; ++l) wsum[tid >> 6][l] = num.w[l];
+    __syncthreads();
+    if (tid != 0) return;
+    for (int w = 1; w < FIN_THREADS / 64; ++w) {
+        mw::Int<NLR> o;
+#pragma unroll
+        for (int l = 0; l < NLR; ++l) o.w[l] = wsum[w][l];
+        mw::add(num, o);
+    }
     // exact division by den = 2^shift * odd
     mw::sar(num, c_shift[k][p]);
     mw::Int<NLR> inv;
@@ -97,9 +120,9 @@ __global__ void __launch_bounds__(64) finish_kernel(FinishArgs a) {
 
 hipError_t launch_finish(int nlr, const FinishArgs &a, hipStream_t st) {
     const dim3 grid(n_moments(a.K), a.nvol);
-    if (nlr == 4) hipLaunchKernelGGL((finish_kernel<4>), grid, dim3(64), 0, st, a);
-    else if (nlr == 8) hipLaunchKernelGGL((finish_kernel<8>), grid, dim3(64), 0, st, a);
-    else if (nlr == 12) hipLaunchKernelGGL((finish_kernel<12>), grid, dim3(64), 0, st, a);
+    if (nlr == 4) hipLaunchKernelGGL((finish_kernel<4>), grid, dim3(FIN_THREADS), 0, st, a);
+    else if (nlr == 8) hipLaunchKernelGGL((finish_kernel<8>), grid, dim3(FIN_THREADS), 0, st, a);
+    else if (nlr == 12) hipLaunchKernelGGL((finish_kernel<12>), grid, dim3(FIN_THREADS), 0, st, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -98,17 +98,21 @@ __device__ __forceinline__ void add_shifted(mw::Int<N> &acc, uint32_t v, int shi
     }
 }
 
-// Epilogue shared by both paths.  Thread t holds R[j] = r(item t % 16, slot, k) for
-// k = d + t / 16 + 16 j; the 16 lanes of one k are one aligned lane group.  For every
-// q <= K - k the group sums y^q R exactly and its first lane stores T(tile, k, q).
-template <int NLS, int NLR, int NJ>
+// Epilogue shared by both paths, for a workgroup of T threads.  Thread t holds
+// R[j] = r(item t % 16, slot, k) for k = d + t / 16 + (T / 16) j; the 16 lanes of one k
+// are one aligned lane group.  For every q <= K - k the group sums y^q R exactly and
+// its first lane stores T(tile, k, q).
+template <int T>
+constexpr int epi_nj() { return (KMAX + 1 + T / 16 - 1) / (T / 16); }
+
+template <int T, int NLS, int NLR, int NJ>
 __device__ __forceinline__ void yweight_store(const PowerArgs &a, const TileInfo &ti, int tile, int d,
                                               const mw::Int<NLS> (&R)[NJ]) {
     const int tid = threadIdx.x, ei = tid & 15, K = a.K;
     const uint32_t y = (uint32_t)((ti.ybase + ei) / ti.ydiv);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const int k = d + (tid >> 4) + 16 * j;
+        const int k = d + (tid >> 4) + (T / 16) * j;
         if (k > K) break;  // uniform over the lane group
         mw::Int<NLR> v = mw::resize<NLR, NLS>(R[j]);  // r >= 0
         uint32_t *dst = a.part + ((size_t)tile * (K + 1) + k) * (K + 1) * NLR;
@@ -129,14 +133,17 @@ __device__ __forceinline__ void yweight_store(const PowerArgs &a, const TileInfo
     }
 }
 
-// One workgroup per tile (16 items x one slot).  The four waves split the K-steps of
-// 64 coordinates; their int32 limb-pair sums meet in LDS; then every thread
-// reassembles one (item, k) sum.
+// One workgroup per tile (16 items x one slot).  The waves split the K-steps of 64
+// coordinates (wave w takes steps w, w + W, ...), loading PW_PF steps at once; their
+// int32 limb-pair sums meet in LDS; then every thread reassembles one (item, k) sum.
+constexpr int PW_MW = 8;   // waves of the matrix-core kernel
+constexpr int PW_PF = 3;   // K-steps per wave whose loads are in flight together
 constexpr int PW_NTP = 4;  // 16-column tiles per pass (4 P-limbs x 4 tiles x 4 = 64 VGPRs)
 
 template <int NLS, int NLR>
-__global__ void __launch_bounds__(PW_WAVES * 64) power_mfma_kernel(PowerArgs a) {
+__global__ void __launch_bounds__(PW_MW * 64) power_mfma_kernel(PowerArgs a) {
     typedef int v4i __attribute__((ext_vector_type(4)));
+    constexpr int T = PW_MW * 64;
     __shared__ int32_t ctab[4][PW_NTP][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     TileInfo ti;
@@ -150,70 +157,64 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_mfma_kernel(PowerArgs a) 
     const int nt = a.pow.nt;
     const uint4 *bt = a.pow.b + lane;
 
-    // reassembly work of this thread: (item, k) = (tid & 15, d + (tid >> 4) + 16 j)
+    // reassembly work of this thread: (item, k) = (tid & 15, d + (tid >> 4) + (T / 16) j)
     const int ei = tid & 15;
-    constexpr int NJ = (KMAX + 16) / 16;
+    constexpr int NJ = epi_nj<T>();
     mw::Int<NLS> R[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) mw::set_zero(R[j]);
 
-    auto load_rows = [&](int ks, uint4 (&q)[4]) {
-        if (iv && ks < nks) {
-            const uint4 *p = reinterpret_cast<const uint4 *>(rp + ks * 64);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) q[i] = p[i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) q[i] = make_uint4(0u, 0u, 0u, 0u);
-        }
-    };
-
     for (int t0 = 0; t0 < nt; t0 += PW_NTP) {
-        for (int i = tid; i < 4 * PW_NTP * 256; i += PW_WAVES * 64) (&ctab[0][0][0])[i] = 0;
+        for (int i = tid; i < 4 * PW_NTP * 256; i += T) (&ctab[0][0][0])[i] = 0;
         __syncthreads();
         v4i acc[4][PW_NTP];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int tp = 0; tp < PW_NTP; ++tp) acc[c][tp] = v4i{0, 0, 0, 0};
-        auto load_b = [&](int ks, uint4 (&q)[PW_NTP]) {
+        for (int ks0 = wave; ks0 < nks; ks0 += PW_PF * PW_MW) {
+            uint4 rq[PW_PF][4], bq[PW_PF][PW_NTP];
 #pragma unroll
-            for (int tp = 0; tp < PW_NTP; ++tp)
-                q[tp] = (ks < nks && t0 + tp < nt) ? bt[((size_t)ks * nt + t0 + tp) * 64] : make_uint4(0u, 0u, 0u, 0u);
-        };
-        uint4 cur[4], nxt[4], bq[PW_NTP], bn[PW_NTP];
-        load_rows(wave, cur);
-        load_b(wave, bq);
-        for (int ks = wave; ks < nks; ks += PW_WAVES) {
-            load_rows(ks + PW_WAVES, nxt);  // next K-step of this wave in flight
-            load_b(ks + PW_WAVES, bn);
-            const uint32_t v[16] = {cur[0].x, cur[0].y, cur[0].z, cur[0].w, cur[1].x, cur[1].y, cur[1].z, cur[1].w,
-                                    cur[2].x, cur[2].y, cur[2].z, cur[2].w, cur[3].x, cur[3].y, cur[3].z, cur[3].w};
-            v4i A[4];
+            for (int f = 0; f < PW_PF; ++f) {
+                const int ks = ks0 + f * PW_MW;
+                const bool ok = ks < nks;
+                const uint4 *p = reinterpret_cast<const uint4 *>(rp + ks * 64);
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+                for (int i = 0; i < 4; ++i) rq[f][i] = (ok && iv) ? p[i] : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    uint32_t w = 0;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) w |= ((v[4 * e + i] >> (7 * c)) & 0x7fu) << (8 * i);
-                    A[c][e] = (int)w;
-                }
-#pragma unroll
-            for (int tp = 0; tp < PW_NTP; ++tp) {
-                if (t0 + tp < nt) {
-                    v4i B;
-                    __builtin_memcpy(&B, &bq[tp], 16);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[c][tp] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[c], B, acc[c][tp], 0, 0, 0);
-                }
+                for (int tp = 0; tp < PW_NTP; ++tp)
+                    bq[f][tp] = (ok && t0 + tp < nt) ? bt[((size_t)ks * nt + t0 + tp) * 64] : make_uint4(0u, 0u, 0u, 0u);
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) cur[i] = nxt[i];
+            for (int f = 0; f < PW_PF; ++f) {
+                if (ks0 + f * PW_MW >= nks) break;
+                const uint32_t v[16] = {rq[f][0].x, rq[f][0].y, rq[f][0].z, rq[f][0].w,
+                                        rq[f][1].x, rq[f][1].y, rq[f][1].z, rq[f][1].w,
+                                        rq[f][2].x, rq[f][2].y, rq[f][2].z, rq[f][2].w,
+                                        rq[f][3].x, rq[f][3].y, rq[f][3].z, rq[f][3].w};
+                v4i A[4];
 #pragma unroll
-            for (int tp = 0; tp < PW_NTP; ++tp) bq[tp] = bn[tp];
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        uint32_t w = 0;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) w |= ((v[4 * e + i] >> (7 * c)) & 0x7fu) << (8 * i);
+                        A[c][e] = (int)w;
+                    }
+#pragma unroll
+                for (int tp = 0; tp < PW_NTP; ++tp) {
+                    if (t0 + tp < nt) {
+                        v4i B;
+                        __builtin_memcpy(&B, &bq[f][tp], 16);
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            acc[c][tp] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[c], B, acc[c][tp], 0, 0, 0);
+                    }
+                }
+            }
         }
-        // partial limb-pair sums of the four waves -> ctab[c][tile][item][col]
+        // partial limb-pair sums of the waves -> ctab[c][tile][item][col]
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -226,7 +227,7 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_mfma_kernel(PowerArgs a) 
         const int colp0 = t0 * 16, colp1 = (t0 + PW_NTP) * 16;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const int k = d + (tid >> 4) + 16 * j;
+            const int k = d + (tid >> 4) + (T / 16) * j;
             if (k > K) break;
             const int cs0 = a.pow.colstart[k], cs1 = a.pow.colstart[k + 1];
             const int lo = cs0 > colp0 ? cs0 : colp0, hi = cs1 < colp1 ? cs1 : colp1;
@@ -243,7 +244,7 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_mfma_kernel(PowerArgs a) 
         }
         __syncthreads();
     }
-    yweight_store<NLS, NLR, NJ>(a, ti, blockIdx.x, d, R);
+    yweight_store<T, NLS, NLR, NJ>(a, ti, blockIdx.x, d, R);
 }
 
 template <int NLS, int NLR>
@@ -292,21 +293,22 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_valu_kernel(PowerArgs a) 
         }
     }
     __syncthreads();
-    constexpr int NJ = (KMAX + 16) / 16;
+    constexpr int T = PW_WAVES * 64;
+    constexpr int NJ = epi_nj<T>();
     mw::Int<NLS> R[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const int k = d + (tid >> 4) + 16 * j;
+        const int k = d + (tid >> 4) + (T / 16) * j;
 #pragma unroll
         for (int l = 0; l < NLS; ++l) R[j].w[l] = k <= K ? rbuf[tid & 15][k][l] : 0u;
     }
-    yweight_store<NLS, NLR, NJ>(a, ti, blockIdx.x, d, R);
+    yweight_store<T, NLS, NLR, NJ>(a, ti, blockIdx.x, d, R);
 }
 
 template <int NLS, int NLR>
 static hipError_t power_go(const PowerArgs &a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
-    if (a.pow.b) hipLaunchKernelGGL((power_mfma_kernel<NLS, NLR>), dim3(a.ntiles), dim3(PW_WAVES * 64), 0, st, a);
+    if (a.pow.b) hipLaunchKernelGGL((power_mfma_kernel<NLS, NLR>), dim3(a.ntiles), dim3(PW_MW * 64), 0, st, a);
     else hipLaunchKernelGGL((power_valu_kernel<NLS, NLR>), dim3(a.ntiles), dim3(PW_WAVES * 64), 0, st, a);
     return hipGetLastError();
 }

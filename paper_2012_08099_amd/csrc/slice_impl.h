@@ -168,24 +168,51 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
     });
     const int32_t yz_off = ig.yz_off, yz_stride = ig.yz_stride;
 
-    auto load_unit = [&](Vec(&buf)[T], int64_t u) {
-        const int64_t ct = u / nch, ch = u % nch;
-        const int64_t x0 = ct * 64 * G + (int64_t)r * G;
+    // unit u = ct * nch + ch: column tile ct, T-row chunk ch.  Positions advance by
+    // counters (no divisions in the loop); a unit's first row pointer is kept per lane.
+    struct Pos {
+        int32_t ct, ch;
+        const VT *p;  // row zs + ch * T of this lane's voxels
+    };
+    const int64_t chunk_step = (int64_t)T * pitch_z;
+    auto pos_of = [&](int64_t u) {
+        Pos q;
+        q.ct = (int32_t)(u / nch);
+        q.ch = (int32_t)(u - (int64_t)q.ct * nch);
+        q.p = slice + (zs + (int64_t)q.ch * T) * pitch_z + ((int64_t)q.ct * 64 * G + (int64_t)r * G);
+        return q;
+    };
+    auto next_pos = [&](Pos q) {
+        ++q.ch;
+        q.p += chunk_step;
+        if (q.ch == nch) {
+            q.ch = 0;
+            ++q.ct;
+            q.p = slice + zs * pitch_z + ((int64_t)q.ct * 64 * G + (int64_t)r * G);
+        }
+        return q;
+    };
+
+    auto load_unit = [&](Vec(&buf)[T], const Pos &q) {
+        const int64_t x0 = (int64_t)q.ct * 64 * G + (int64_t)r * G;
         const bool valid = x0 < L;
-        const int64_t zc0 = zs + ch * T;
+        const int64_t zc0 = zs + (int64_t)q.ch * T;
         StaticFor<0, T>::run([&](auto tc) {
             constexpr int t = decltype(tc)::value;
-            const int64_t z = zc0 + t;
-            const bool in = FAST ? true : (valid && z < ze);
-            buf[t] = load_lane<VT, FAST>(slice + (FAST ? z : (z < ze ? z : ze - 1)) * pitch_z, x0, L, in);
+            if constexpr (FAST) {
+                buf[t] = load_lane<VT, true>(q.p + t * pitch_z, 0, L, true);
+            } else {
+                const int64_t z = zc0 + t;
+                const bool in = valid && z < ze;
+                buf[t] = load_lane<VT, false>(slice + (z < ze ? z : ze - 1) * pitch_z, x0, L, in);
+            }
         });
     };
 
-    auto process_unit = [&](const Vec(&dat)[T], int64_t u) {
-        const int64_t ct = u / nch, ch = u % nch;
-        const int64_t x0 = ct * 64 * G + (int64_t)r * G;
+    auto process_unit = [&](const Vec(&dat)[T], const Pos &q, bool last_in_tile) {
+        const int32_t x0 = q.ct * 64 * G + r * G;
         const bool valid = x0 < L;
-        const int64_t zc0 = zs + ch * T;
+        const int32_t zc0 = (int32_t)zs + q.ch * T;
         uint32_t yzs[T];
         StaticFor<0, T>::run([&](auto tc) {
             constexpr int t = decltype(tc)::value;
@@ -246,8 +273,7 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
         }
         // XY: flush when the next unit of this sub-row is in another column tile
         if constexpr (Tr::has_xy) {
-            const bool last = (u + 1 >= u_end) || ((u + 1) / nch != ct);
-            if (last) {
+            if (last_in_tile) {
                 if (FAST || valid) {
                     const uint32_t x0u = (uint32_t)x0;
                     uint32_t *base = lds + coff[0] + (x0u + x0u / 8);
@@ -264,14 +290,18 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
 
     // two units in flight: the loads of unit u+1 are issued before unit u is summed
     Vec bufA[T], bufB[T];
-    int64_t u = u_begin;
-    if (u < u_end) load_unit(bufA, u);
-    for (; u < u_end; u += 2) {
-        if (u + 1 < u_end) load_unit(bufB, u + 1);
-        process_unit(bufA, u);
-        if (u + 1 >= u_end) break;
-        if (u + 2 < u_end) load_unit(bufA, u + 2);
-        process_unit(bufB, u + 1);
+    if (u_begin >= u_end) return;
+    const int32_t n = (int32_t)(u_end - u_begin);
+    Pos pa = pos_of(u_begin), pb;
+    load_unit(bufA, pa);
+    for (int32_t k = 0; k < n; k += 2) {
+        pb = next_pos(pa);
+        if (k + 1 < n) load_unit(bufB, pb);
+        process_unit(bufA, pa, k + 1 >= n || pb.ct != pa.ct);
+        if (k + 1 >= n) break;
+        pa = next_pos(pb);
+        if (k + 2 < n) load_unit(bufA, pa);
+        process_unit(bufB, pb, k + 2 >= n || pa.ct != pb.ct);
     }
 }
 
@@ -379,9 +409,15 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
             const int32_t len = slot_len[s];
             if (len == 0) continue;
             const SegView v = seg_view(lds, ig, i, side, d == 1);
-            int32_t *dst = rows_out + slot_off[s];
-            for (int32_t a = tid; a < len; a += NW * 64)
-                dst[a] = (int32_t)((a >= v.alo && a <= v.ahi) ? seg_value(v, a) : 0u);
+            // 16-byte stores: len is a multiple of 64 and the rows are 256-byte aligned
+            int4 *dst = reinterpret_cast<int4 *>(rows_out + slot_off[s]);
+            for (int32_t a = 4 * tid; a < len; a += 4 * NW * 64) {
+                int32_t e[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    e[c] = (int32_t)((a + c >= v.alo && a + c <= v.ahi) ? seg_value(v, a + c) : 0u);
+                dst[a >> 2] = make_int4(e[0], e[1], e[2], e[3]);
+            }
         }
     });
 }
