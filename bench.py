@@ -8,7 +8,10 @@ per-slice power sums (one HBM pass), y-reduction to 2D moments, recombination in
 HBM.  Three distinct volumes are rotated so repeated steps are not served from the
 256 MB Infinity Cache.  Prints ONE JSON line on stdout; everything else goes to stderr.
 
-The headline loop runs the K steps back to back.  A second pass over the same K steps
+The headline loop issues the K steps round-robin on --streams streams (default 2), each
+with its own workspace, so one volume's power sums and recombination overlap the next
+volume's projection; the single-stream time per volume is reported beside it
+(latency_ms_single_stream).  A further pass over the same K steps
 records the library's HIP events between the kernels (on the stream they run on) and
 gives the stage breakdown.  The roofline figure is for the dominant kernel (the
 projection, one pass over the volume): algorithmic bytes = every voxel read once
@@ -105,6 +108,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="ct512_k6", choices=sorted(WORKLOADS))
     ap.add_argument("--nvol", type=int, default=3, help="distinct volumes rotated between steps")
+    ap.add_argument("--streams", type=int, default=2,
+                    help="volumes in flight (one stream and workspace each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -129,37 +134,49 @@ def main(argv=None):
         vols.append(v.contiguous())
     nm, nm4 = dpm.num_moments(K), dpm.num_moments(min(K, 4))
     code = 1 if dt == "u8" else 2
-    ws = torch.empty(dpm.workspace_bytes(shape, code, K), dtype=torch.uint8, device="cuda:0")
-    ex = torch.empty((nm4, 2), dtype=torch.int64, device="cuda:0")
-    fp = torch.empty(nm, dtype=torch.float64, device="cuda:0")
+    depth = max(1, a.streams)
+    wsb = dpm.workspace_bytes(shape, code, K)
+    ws = [torch.empty(wsb, dtype=torch.uint8, device="cuda:0") for _ in range(depth)]
+    ex = [torch.empty((nm4, 2), dtype=torch.int64, device="cuda:0") for _ in range(depth)]
+    fp = [torch.empty(nm, dtype=torch.float64, device="cuda:0") for _ in range(depth)]
+    streams = [torch.cuda.Stream(device="cuda:0") for _ in range(depth)]  # default priority
     plan = dpm.plan(shape, code, K)
     log("plan", plan)
 
-    for i in range(a.warmup):
-        dpm.moments_async(vols[i % a.nvol], K, ex, fp, ws)
-    torch.cuda.synchronize()
+    def run(n, nstreams):
+        """n steps, step i on stream i % nstreams with that stream's workspace/outputs."""
+        main = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(main)
+        for s in streams[:nstreams]:
+            s.wait_event(e0)
+        for i in range(n):
+            j = i % nstreams
+            dpm.moments_async(vols[i % a.nvol], K, ex[j], fp[j], ws[j], stream=streams[j])
+        for s in streams[:nstreams]:
+            main.wait_stream(s)
+        e1.record(main)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
 
-    # headline: K steps back to back, nothing else on the stream
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for i in range(a.steps):
-        dpm.moments_async(vols[i % a.nvol], K, ex, fp, ws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    run(a.warmup, depth)
+    # headline: K steps, consecutive volumes on `depth` streams so that one volume's
+    # power sums and recombination overlap the next volume's projection
+    ms = run(a.steps, depth)
     ms_step = ms / a.steps
     voxels = N * M * L
     value = voxels * a.steps / (ms / 1e3)
+    # latency of one volume alone: the same K steps on a single stream
+    ms_serial = run(a.steps, 1) / a.steps
 
-    # stage breakdown: the same K steps again with the library's HIP events recorded
-    # between the kernels on their stream (the events themselves add small gaps, which
-    # is why the headline loop runs without them)
+    # stage breakdown: the same K steps again on one stream with the library's HIP
+    # events recorded between the kernels (the events themselves add small gaps, which
+    # is why the timed loops run without them)
     dpm.profile_collect()
     dpm.profile_enable(True)
     for i in range(a.steps):
-        dpm.moments_async(vols[i % a.nvol], K, ex, fp, ws)
+        dpm.moments_async(vols[i % a.nvol], K, ex[0], fp[0], ws[0], stream=streams[0])
     torch.cuda.synchronize()
     dpm.profile_enable(False)
     prof = dpm.profile_collect()
@@ -170,9 +187,9 @@ def main(argv=None):
     shash = source_hash()
     traffic = read_traffic(a.workload, shash)
 
-    # sanity: last result equals a fresh blocking call on the same volume
+    # sanity: the last result equals a fresh blocking call on the same volume
     res = dpm.moments(vols[(a.steps - 1) % a.nvol], K)
-    assert res.exact == dpm._exact_from_tensor(ex)
+    assert res.exact == dpm._exact_from_tensor(ex[0])
 
     out = {
         "metric": "voxels/s (512^3 uint16, orders <= 6)" if a.workload == "ct512_k6" else f"voxels/s ({a.workload})",
@@ -182,13 +199,15 @@ def main(argv=None):
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": ms_step,
+        "latency_ms_single_stream": ms_serial,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u16" if elem == 2 else "u8",
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {L}x{M}x{N} {dt} CT-like phantom, max_order {K} "
-                               f"({nm} moments; orders<=4 exact int128, all FP64)", "volumes_rotated": a.nvol},
+                               f"({nm} moments; orders<=4 exact int128, all FP64)", "volumes_rotated": a.nvol,
+                   "streams": depth},
         "hbm_gbs_algorithmic": voxels * elem / (ms_step / 1e3) / 1e9,
         "stages_ms": {"project": proj_ms, "power": prof["ms_power"] / max(prof["calls"], 1),
                       "combine": prof["ms_combine"] / max(prof["calls"], 1),

@@ -146,17 +146,26 @@ MW_HD Int<N> mul_i64(const Int<N> &a, int64_t m) {
     return r;
 }
 
+// limb k of a, or `fill` when k is outside [0, N) (k may be a runtime value: the limbs
+// are selected with compile-time indices so that they stay in registers)
+template <int N>
+MW_HD uint32_t limb_or(const Int<N> &a, int k, uint32_t fill) {
+    uint32_t r = fill;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r = (k == i) ? a.w[i] : r;
+    return r;
+}
+
 // arithmetic shift right by s, 0 <= s < 32N
 template <int N>
 MW_HD void sar(Int<N> &a, int s) {
-    uint32_t ext = is_neg(a) ? 0xffffffffu : 0u;
-    int ws = s >> 5, bs = s & 31;
+    const uint32_t ext = is_neg(a) ? 0xffffffffu : 0u;
+    const int ws = s >> 5, bs = s & 31;
     Int<N> r;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        int j = i + ws;
-        uint32_t lo = j < N ? a.w[j] : ext;
-        uint32_t hi = (j + 1) < N ? a.w[j + 1] : ext;
+        const uint32_t lo = limb_or(a, i + ws, ext);
+        const uint32_t hi = limb_or(a, i + ws + 1, ext);
         r.w[i] = bs ? ((lo >> bs) | (hi << (32 - bs))) : lo;
     }
     a = r;
@@ -190,12 +199,16 @@ MW_HD double to_double(const Int<N> &a) {
     bool negv = is_neg(m);
     if (negv) neg(m);
     int top = -1;
+    uint32_t topw = 0;
 #pragma unroll
     for (int i = 0; i < N; ++i)
-        if (m.w[i]) top = i;
+        if (m.w[i]) {
+            top = i;
+            topw = m.w[i];
+        }
     if (top < 0) return 0.0;
     // 64-bit window holding the leading one, plus a sticky bit for what lies below
-    int lz = __builtin_clz(m.w[top]);
+    int lz = __builtin_clz(topw);
     int msb = top * 32 + (31 - lz);  // index of the leading one
     uint64_t win;
     bool sticky = false;

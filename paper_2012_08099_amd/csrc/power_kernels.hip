@@ -136,7 +136,7 @@ __device__ __forceinline__ void yweight_store(const PowerArgs &a, const TileInfo
 // One workgroup per tile (16 items x one slot).  The waves split the K-steps of 64
 // coordinates (wave w takes steps w, w + W, ...), loading PW_PF steps at once; their
 // int32 limb-pair sums meet in LDS; then every thread reassembles one (item, k) sum.
-constexpr int PW_MW = 8;   // waves of the matrix-core kernel
+constexpr int PW_MW = 4;   // waves of the matrix-core kernel
 constexpr int PW_PF = 3;   // K-steps per wave whose loads are in flight together
 constexpr int PW_NTP = 4;  // 16-column tiles per pass (4 P-limbs x 4 tiles x 4 = 64 VGPRs)
 
