@@ -159,6 +159,80 @@ typedef struct {
 int dpm_profile_enable(int on);
 int dpm_profile_collect(dpm_profile *out);
 
+/* ---- served loop ---------------------------------------------------------------
+ * A request server for a stream of independent volumes of mixed sizes: the batched
+ * and served workloads of a moment service (the paper computes one volume at a time;
+ * every request here is that computation, eq. 2 via Sections 3.1-3.2).
+ *
+ * The server owns one device arena of `hbm_budget` bytes, `n_streams` HIP streams and
+ * a worker thread.  Requests are admitted first come, first served, when their device
+ * blocks (copied volume if it arrives in host memory, workspace, device outputs) fit in
+ * the arena; a request whose blocks can never fit is refused at submit (DPM_ERANGE).
+ * Requests of at most `batch_voxels` voxels and order <= 6 that are waiting together are
+ * served by one dpm_moments_batched launch sequence (up to `batch_max` of them);
+ * larger ones by dpm_moments_async.  Jobs go to the stream with the fewest jobs in
+ * flight.  Results are copied to the caller's host buffers before the completion is
+ * reported.
+ *
+ * Ownership: the caller keeps `data` and the output buffers of a request valid until
+ * its completion has been returned by dpm_server_poll.  A request's `data` may be host
+ * memory (copied to the arena) or device memory on the server's device (read in place;
+ * batched requests are copied into a packed arena block first).
+ * Thread safety: submit and poll may be called from any threads.
+ * Errors: submit returns DPM_EINVAL for a malformed request and DPM_ERANGE if it cannot
+ * fit the budget; a request that fails on the device completes with its status. */
+typedef struct {
+    int32_t device;          /* HIP device ordinal                                      */
+    int32_t n_streams;       /* streams used for jobs (>= 1)                            */
+    int64_t hbm_budget;      /* bytes of device memory for the arena                    */
+    int64_t batch_voxels;    /* requests of at most this many voxels may be batched     */
+    int32_t batch_max;       /* most requests in one batched launch                     */
+    int32_t max_inflight;    /* most jobs in flight (pinned result slots)               */
+} dpm_server_config;
+
+typedef struct dpm_server dpm_server;  /* opaque */
+
+typedef struct {
+    const void *data;        /* contiguous V[z][y][x]                                   */
+    int32_t data_on_device;  /* 1: device pointer on the server's device, 0: host memory */
+    int32_t dtype;           /* dpm_dtype                                               */
+    int64_t dims[3];         /* L, M, N                                                 */
+    int32_t max_order;       /* 0..16 (batched only when <= 6)                          */
+    int32_t reserved;
+    uint64_t tag;            /* returned with the completion                            */
+    double t_arrival_ms;     /* arrival time on the server clock (dpm_server_now_ms);
+                                <= 0: the submit time                                  */
+    dpm_i128 *exact;         /* host, n_moments(min(K,4)) entries, or NULL              */
+    double *fp64;            /* host, n_moments(K) entries, or NULL                     */
+} dpm_request;
+
+typedef struct {
+    uint64_t tag;
+    int32_t status;          /* DPM_OK or the failure                                   */
+    int32_t batched;         /* 1: served in a batched launch                           */
+    double t_arrival_ms;     /* server clock                                            */
+    double t_start_ms;       /* first device work issued                                */
+    double t_done_ms;        /* results in the caller's buffers                         */
+} dpm_completion;
+
+typedef struct {
+    int64_t submitted, completed, batched_jobs, single_jobs;
+    int64_t arena_bytes, arena_peak_used;
+    int32_t pending, inflight;
+} dpm_server_stats;
+
+/* Milliseconds on the server clock (monotonic). */
+double dpm_server_now_ms(void);
+int dpm_server_create(const dpm_server_config *cfg, dpm_server **out);
+int dpm_server_submit(dpm_server *s, const dpm_request *req);
+/* Up to `max` completions; waits up to wait_ms (0: no wait) for the first one.  Returns
+ * the number written, or a negative status. */
+int dpm_server_poll(dpm_server *s, dpm_completion *out, int max, int wait_ms);
+int dpm_server_stats_get(dpm_server *s, dpm_server_stats *out);
+/* Waits for every submitted request, then frees the server (completions not yet
+ * polled are dropped). */
+int dpm_server_destroy(dpm_server *s);
+
 /* ---- introspection used by the host-side tests ------------------------------ */
 
 /* Exact recombination weight of Section 3.2 generalised: for total x-z degree k,

@@ -224,3 +224,84 @@ def profile_collect():
 
 def release():
     check(lib().dpm_release(), "dpm_release")
+
+
+class Server:
+    """The served loop of ``dpm_server_*`` (argument marshalling only).
+
+    ``submit`` takes a contiguous uint8/uint16 array -- a device tensor (read in place)
+    or a host tensor / numpy array (copied into the server's arena; pinned memory keeps
+    that copy asynchronous) -- and returns a tag.  The input and the result arrays are
+    kept alive here until ``poll`` has returned the request's completion.
+    """
+
+    def __init__(self, hbm_budget=8 << 30, n_streams=4, batch_voxels=128 ** 3, batch_max=256,
+                 max_inflight=16, device=0):
+        cfg = _lib.ServerConfig(int(device), int(n_streams), int(hbm_budget), int(batch_voxels), int(batch_max),
+                                int(max_inflight))
+        h = ctypes.c_void_p()
+        check(lib().dpm_server_create(ctypes.byref(cfg), ctypes.byref(h)), "dpm_server_create")
+        self._h = h
+        self._next = 1
+        self._live = {}  # tag -> (input, exact, fp64, K)
+
+    @staticmethod
+    def now_ms():
+        return lib().dpm_server_now_ms()
+
+    def submit(self, vol, K, t_arrival_ms=0.0):
+        import numpy as np
+        import torch
+        if isinstance(vol, np.ndarray):
+            vol = torch.from_numpy(np.ascontiguousarray(vol.view(np.int16) if vol.dtype == np.uint16 else vol))
+        if not vol.is_contiguous() or vol.dim() != 3:
+            raise ValueError("volume must be a contiguous 3D tensor (N, M, L)")
+        on_dev = vol.is_cuda
+        exact = np.zeros((num_moments(min(K, 4)), 2), dtype=np.int64)
+        fp = np.zeros(num_moments(K), dtype=np.float64)
+        tag = self._next
+        self._next += 1
+        req = _lib.Request()
+        req.data = vol.data_ptr()
+        req.data_on_device = 1 if on_dev else 0
+        req.dtype = _dtype_code(vol)
+        req.dims[:] = [int(vol.shape[2]), int(vol.shape[1]), int(vol.shape[0])]
+        req.max_order = int(K)
+        req.tag = tag
+        req.t_arrival_ms = float(t_arrival_ms)
+        req.exact = exact.ctypes.data
+        req.fp64 = fp.ctypes.data
+        check(lib().dpm_server_submit(self._h, ctypes.byref(req)), "dpm_server_submit")
+        self._live[tag] = (vol, exact, fp, K)
+        return tag
+
+    def poll(self, max_n=256, wait_ms=0):
+        """Completed requests: list of dicts with tag, status, batched, times and the Moments."""
+        buf = (_lib.Completion * max_n)()
+        n = lib().dpm_server_poll(self._h, buf, max_n, int(wait_ms))
+        if n < 0:
+            raise DpmError(n, "dpm_server_poll")
+        out = []
+        for c in buf[:n]:
+            vol, exact, fp, K = self._live.pop(c.tag)
+            ex = [i128_to_int(int(lo) & (2 ** 64 - 1), int(hi)) for lo, hi in exact.tolist()]
+            out.append({"tag": c.tag, "status": c.status, "batched": bool(c.batched),
+                        "t_arrival_ms": c.t_arrival_ms, "t_start_ms": c.t_start_ms, "t_done_ms": c.t_done_ms,
+                        "moments": Moments(K, ex, fp)})
+        return out
+
+    def stats(self):
+        s = _lib.ServerStats()
+        check(lib().dpm_server_stats_get(self._h, ctypes.byref(s)), "dpm_server_stats_get")
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def close(self):
+        if self._h:
+            check(lib().dpm_server_destroy(self._h), "dpm_server_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

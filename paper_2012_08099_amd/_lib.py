@@ -58,6 +58,29 @@ class Profile(ctypes.Structure):
                 ("ms_total", ctypes.c_double)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("hbm_budget", ctypes.c_int64),
+                ("batch_voxels", ctypes.c_int64), ("batch_max", ctypes.c_int32), ("max_inflight", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("data_on_device", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("dims", ctypes.c_int64 * 3), ("max_order", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tag", ctypes.c_uint64), ("t_arrival_ms", ctypes.c_double), ("exact", ctypes.c_void_p),
+                ("fp64", ctypes.c_void_p)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("batched", ctypes.c_int32),
+                ("t_arrival_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double), ("t_done_ms", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batched_jobs", ctypes.c_int64),
+                ("single_jobs", ctypes.c_int64), ("arena_bytes", ctypes.c_int64), ("arena_peak_used", ctypes.c_int64),
+                ("pending", ctypes.c_int32), ("inflight", ctypes.c_int32)]
+
+
 Dims = ctypes.c_int64 * 3
 
 # exported symbol -> (restype, argtypes)
@@ -87,6 +110,12 @@ SIGNATURES = {
     "dpm_profile_collect": (ctypes.c_int, [ctypes.POINTER(Profile)]),
     "dpm_plan": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(PlanInfo)]),
+    "dpm_server_now_ms": (ctypes.c_double, []),
+    "dpm_server_create": (ctypes.c_int, [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]),
+    "dpm_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request)]),
+    "dpm_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Completion), ctypes.c_int, ctypes.c_int]),
+    "dpm_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "dpm_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 _lib = None

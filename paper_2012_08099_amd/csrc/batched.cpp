@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -48,6 +49,32 @@ struct BPlan {
 };
 
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+// Pinned staging for the descriptor upload, so the call stays asynchronous: a buffer
+// is reused only once the event recorded after its copy has fired.
+struct Staging {
+    void *p = nullptr;
+    size_t n = 0;
+    int dev = -1;
+    hipEvent_t ev = nullptr;
+};
+std::mutex g_stage_mu;
+std::vector<Staging> g_stage;
+
+Staging *stage_acquire(size_t n, int dev) {
+    for (auto &s : g_stage)
+        if (s.dev == dev && s.n >= n && hipEventQuery(s.ev) == hipSuccess) return &s;
+    Staging s;
+    s.n = std::max<size_t>(n, 1 << 20);
+    s.dev = dev;
+    if (hipHostMalloc(&s.p, s.n, hipHostMallocDefault) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(s.p);
+        return nullptr;
+    }
+    g_stage.push_back(s);
+    return &g_stage.back();
+}
 
 int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     if (!rois || n <= 0 || K < 0 || K > 6) return K > 6 ? DPM_ENOTSUP : DPM_EINVAL;
@@ -155,6 +182,21 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
 
 }  // namespace
 
+namespace dpm {
+// Frees the pinned staging buffers (called by dpm_release).
+int batched_release() {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    int rc = DPM_OK;
+    for (auto &s : g_stage) {
+        if (hipEventSynchronize(s.ev) != hipSuccess) rc = DPM_EDEVICE;
+        (void)hipEventDestroy(s.ev);
+        if (hipHostFree(s.p) != hipSuccess) rc = DPM_EDEVICE;
+    }
+    g_stage.clear();
+    return rc;
+}
+}  // namespace dpm
+
 extern "C" {
 
 size_t dpm_batched_workspace_bytes(const dpm_roi *rois, int n_rois, int max_order) {
@@ -179,11 +221,21 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
     uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
     PowTab pt{};
     if (p.mfma && (rc = batched_powtab(p.amax, max_order, pt))) return rc;
-    hipError_t e = hipMemcpyAsync(drd, p.rd.data(), sizeof(RoiDesc) * p.rd.size(), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(dit, p.it.data(), sizeof(BatchItem) * p.it.size(), hipMemcpyHostToDevice, st);
-    // pageable sources: make sure the copies have consumed them before returning
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    hipError_t e = hipSuccess;
+    {
+        int dev = 0;
+        e = hipGetDevice(&dev);
+        std::lock_guard<std::mutex> lk(g_stage_mu);
+        const size_t brd = sizeof(RoiDesc) * p.rd.size(), bit = sizeof(BatchItem) * p.it.size();
+        Staging *sg = e == hipSuccess ? stage_acquire(brd + bit, dev) : nullptr;
+        if (!sg) return e == hipSuccess ? DPM_ENOMEM : (batched_set_error((int)e), DPM_EDEVICE);
+        std::memcpy(sg->p, p.rd.data(), brd);
+        std::memcpy(static_cast<uint8_t *>(sg->p) + brd, p.it.data(), bit);
+        e = hipMemcpyAsync(drd, sg->p, brd, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(dit, static_cast<uint8_t *>(sg->p) + brd, bit, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(sg->ev, st);
+    }
     if (e != hipSuccess) {
         batched_set_error((int)e);
         return DPM_EDEVICE;

@@ -453,6 +453,7 @@ int current_device(int &dev) {
 }  // namespace
 
 namespace dpm {
+int batched_release();  // batched.cpp
 int batched_powtab(int amax, int K, PowTab &out) { return get_powtab(amax, K, out); }
 bool batched_pow_columns(int amax, int K, int32_t colstart[KMAX + 2]) { return pow_columns(amax, K, colstart); }
 void batched_prof_mark(int idx, hipStream_t st) {
@@ -610,7 +611,7 @@ int dpm_project_images(const void *volume, const int64_t dims[3], dpm_dtype dtyp
 
 int dpm_release(void) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
-    int rc = DPM_OK;
+    int rc = dpm::batched_release();
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (auto &kv : g_pow) {

@@ -1,0 +1,136 @@
+"""GPU tests of the served loop (dpm_server_*): every request's result equals the same
+volume's single-call result and the oracle; small requests are batched; admission
+respects the device-memory budget; inputs may start on the host or on the device.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_moments_equal, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dpm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2012_08099_amd as m
+    m.lib()
+    return m
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def drain(srv, n, timeout_ms=60000):
+    got = []
+    t0 = srv.now_ms()
+    while len(got) < n:
+        got += srv.poll(256, wait_ms=50)
+        assert srv.now_ms() - t0 < timeout_ms, f"only {len(got)} of {n} completions"
+    return got
+
+
+def mixed_requests(seed, n):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        u = rng.uniform()
+        if u < 0.6:
+            shape = tuple(int(s) for s in rng.integers(3, 40, size=3))
+            V = synth.sphere_mask(shape, rng)
+            K = int(rng.integers(0, 7))
+        elif u < 0.9:
+            shape = tuple(int(s) for s in rng.integers(16, 70, size=3))
+            V = synth.uniform_volume(shape, np.uint16, seed=int(rng.integers(1 << 30)))
+            K = int(rng.integers(2, 9))
+        else:
+            shape = (64, 64, 64)
+            V = synth.mri_phantom(shape, seed=int(rng.integers(1 << 30)))
+            K = int(rng.integers(5, 11))
+        reqs.append((V, K, bool(rng.integers(0, 2))))
+    return reqs
+
+
+def test_server_matches_oracle_mixed(dpm):
+    import torch
+    say("server mixed")
+    reqs = mixed_requests(7, 120)
+    srv = dpm.Server(hbm_budget=1 << 30, n_streams=3, batch_voxels=40 ** 3, batch_max=64)
+    try:
+        tags = {}
+        for V, K, on_dev in reqs:
+            vol = to_dev(V) if on_dev else torch.from_numpy(V.view(np.int16) if V.dtype == np.uint16 else V)
+            tags[srv.submit(vol, K)] = (V, K)
+        done = drain(srv, len(reqs))
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert sorted(c["tag"] for c in done) == sorted(tags)
+    assert stats["batched_jobs"] >= 1 and stats["single_jobs"] >= 1
+    for c in done:
+        V, K = tags[c["tag"]]
+        assert c["status"] == 0
+        assert c["t_arrival_ms"] <= c["t_start_ms"] <= c["t_done_ms"]
+        small = V.size <= 40 ** 3 and K <= 6
+        assert c["batched"] == small
+        assert_moments_equal(c["moments"], oracle.moments_exact(V, K), K, f"tag {c['tag']} {V.shape} K={K}")
+
+
+def test_server_admission_waits_for_budget(dpm):
+    """A budget that holds about one medium job at a time: requests queue, still all
+    complete, in full, and the arena's peak stays inside the budget."""
+    say("server budget")
+    shape = (64, 96, 80)
+    vols = [synth.uniform_volume(shape, np.uint16, seed=s) for s in range(12)]
+    ws = dpm.workspace_bytes(shape, 2, 5)
+    budget = ws + ws // 2 + (64 << 10)  # one job's workspace and outputs, not two
+    srv = dpm.Server(hbm_budget=budget, n_streams=2, batch_voxels=0, batch_max=1)
+    try:
+        tags = {srv.submit(to_dev(V), 5): V for V in vols}
+        done = drain(srv, len(vols))
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert stats["arena_peak_used"] <= budget
+    for c in done:
+        assert c["status"] == 0
+        assert_moments_equal(c["moments"], oracle.moments_exact(tags[c["tag"]], 5), 5, "budget")
+
+
+def test_server_refuses_what_cannot_fit(dpm):
+    srv = dpm.Server(hbm_budget=1 << 20, n_streams=1)
+    try:
+        with pytest.raises(dpm.DpmError):
+            srv.submit(to_dev(np.zeros((128, 128, 128), np.uint16)), 6)
+        with pytest.raises((dpm.DpmError, ValueError)):
+            srv.submit(to_dev(np.zeros((4, 4, 4), np.uint16)), 17)
+    finally:
+        srv.close()
+
+
+def test_server_same_volume_alone_and_in_a_mix(dpm):
+    """One volume's result does not depend on what it was served with."""
+    say("server alone vs mix")
+    V = synth.mri_phantom((40, 36, 44), seed=5)
+    alone = dpm.moments(to_dev(V), 6)
+    srv = dpm.Server(hbm_budget=1 << 30, n_streams=2, batch_voxels=64 ** 3)
+    try:
+        others = [synth.uniform_volume((20, 24, 28), np.uint8, seed=s) for s in range(30)]
+        for i, o in enumerate(others):
+            srv.submit(to_dev(o), 6)
+            if i == 15:
+                t = srv.submit(to_dev(V), 6)
+        done = drain(srv, 31)
+    finally:
+        srv.close()
+    mine = [c for c in done if c["tag"] == t][0]
+    assert mine["batched"]
+    assert mine["moments"].exact == alone.exact
+    assert np.array_equal(mine["moments"].fp64.view(np.uint64), alone.fp64.view(np.uint64))
