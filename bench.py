@@ -101,12 +101,121 @@ def read_traffic(workload, shash):
     return t.get("bytes_per_launch")
 
 
+def serve_main(a):
+    """Served workload: a Poisson stream of mixed requests through dpm_server.
+
+    Mix (per request): 70% uint8 sphere-mask ROIs with dims U{32..128}^3, 25% uint16
+    MRI-like 256x256xZ with Z in [100, 300], 5% 512^3 uint16 CT-like; K = 6.  Volumes
+    come from pools of pre-generated inputs (64 / 8 / 3 distinct).  First the capacity
+    (all requests arriving at once), then Poisson arrivals at 0.5x and 0.8x of it; each
+    with the inputs resident on the device and in pinned host memory (copied per
+    request).  Latency = result in the caller's buffer - scheduled arrival.
+    """
+    import numpy as np
+    import threading
+    import torch
+
+    import paper_2012_08099_amd as dpm
+    import synth
+
+    rng = np.random.default_rng(a.seed)
+    K = 6
+    t0 = time.perf_counter()
+    small = [synth.sphere_mask(tuple(int(v) for v in rng.integers(32, 129, size=3)), rng) for _ in range(64)]
+    mid = [synth.mri_phantom((int(rng.integers(100, 301)), 256, 256), seed=s) for s in range(8)]
+    ct0 = make_volume("ct", (512, 512, 512), "u16", 0)
+    log(f"pools generated in {time.perf_counter() - t0:.1f} s")
+
+    def to_t(V, dev):
+        t = torch.from_numpy(V.view(np.int16) if V.dtype == np.uint16 else V)
+        return t.to("cuda:0") if dev else t.pin_memory()
+
+    results = {}
+    for mode in ("device", "host"):
+        dev = mode == "device"
+        ps = [to_t(V, dev) for V in small]
+        pm = [to_t(V, dev) for V in mid]
+        c0 = to_t(ct0, dev)
+        pc = [c0, torch.flip(c0, dims=[2]).contiguous(), torch.roll(c0, shifts=37, dims=0).contiguous()]
+        if not dev:
+            pc = [t.pin_memory() if not t.is_pinned() else t for t in pc]
+        kinds = rng.choice(3, size=a.requests, p=[0.70, 0.25, 0.05])
+        vols = [ps[int(rng.integers(len(ps)))] if k == 0 else pm[int(rng.integers(len(pm)))] if k == 1
+                else pc[int(rng.integers(len(pc)))] for k in kinds]
+        nvox = sum(int(v.numel()) for v in vols)
+
+        def run(rate_hz):
+            srv = dpm.Server(hbm_budget=a.hbm_budget << 30, n_streams=a.server_streams,
+                             batch_voxels=128 ** 3, batch_max=256, max_inflight=16)
+            try:
+                start = srv.now_ms() + 50.0
+                if rate_hz:
+                    arr = start + np.cumsum(rng.exponential(1e3 / rate_hz, size=len(vols)))
+                else:
+                    arr = np.full(len(vols), start)
+                items = [(v, K, float(t)) for v, t in zip(vols, arr)]
+                th = threading.Thread(target=lambda: srv.replay(items))
+                th.start()
+                done = []
+                while len(done) < len(items):
+                    done += srv.poll(1024, wait_ms=20)
+                th.join()
+                st = srv.stats()
+            finally:
+                srv.close()
+            bad = [c for c in done if c["status"] != 0]
+            assert not bad, f"{len(bad)} requests failed"
+            lat = np.array([c["t_done_ms"] - c["t_arrival_ms"] for c in done])
+            t_first = min(c["t_arrival_ms"] for c in done)
+            t_last = max(c["t_done_ms"] for c in done)
+            span_s = (t_last - t_first) / 1e3
+            return {"offered_per_s": rate_hz, "served_per_s": len(done) / span_s,
+                    "voxels_per_s": nvox / span_s, "p50_ms": float(np.percentile(lat, 50)),
+                    "p99_ms": float(np.percentile(lat, 99)), "batched_jobs": st["batched_jobs"],
+                    "single_jobs": st["single_jobs"], "arena_peak_gib": st["arena_peak_used"] / 2 ** 30}
+
+        cap = run(0.0)
+        log(mode, "capacity", cap)
+        r50 = run(0.5 * cap["served_per_s"])
+        log(mode, "0.5x", r50)
+        r80 = run(0.8 * cap["served_per_s"])
+        log(mode, "0.8x", r80)
+        # plain path for reference: one request after another on one stream
+        ws_b = max(dpm.workspace_bytes(tuple(v.shape), 2 if v.dtype == torch.int16 else 1, K) for v in vols[:200])
+        ws = torch.empty(ws_b, dtype=torch.uint8, device="cuda:0")
+        ex = torch.empty((35, 2), dtype=torch.int64, device="cuda:0")
+        fp = torch.empty(84, dtype=torch.float64, device="cuda:0")
+        plain = vols[:200] if dev else [v.to("cuda:0", non_blocking=True) for v in vols[:200]]
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        for v in plain:
+            dpm.moments_async(v, K, ex, fp, ws)
+        torch.cuda.synchronize()
+        plain_s = (time.perf_counter() - tp) / len(plain)
+        results[mode] = {"capacity": cap, "poisson_0.5x": r50, "poisson_0.8x": r80,
+                         "plain_serial_per_s": 1.0 / plain_s}
+        del ps, pm, pc, vols, plain
+        torch.cuda.empty_cache()
+
+    out = {"metric": "served requests/s (mix 70% u8 ROI 32-128^3 / 25% u16 256x256xZ / 5% 512^3 u16, K=6)",
+           "value": results["device"]["capacity"]["served_per_s"], "unit": "requests/s", "n_gpus": 1,
+           "higher_is_better": True, "data": "synthetic", "requests": a.requests,
+           "config": {"workload": "serve_mix", "hbm_budget_gib": a.hbm_budget, "server_streams": a.server_streams},
+           "modes": results}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="ct512_k6", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="ct512_k6", choices=sorted(WORKLOADS) + ["serve_mix"])
+    ap.add_argument("--requests", type=int, default=10000, help="serve_mix: requests per run")
+    ap.add_argument("--hbm-budget", type=int, default=16, help="serve_mix: server arena, GiB")
+    ap.add_argument("--server-streams", type=int, default=4, help="serve_mix: server streams")
+    ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--nvol", type=int, default=3, help="distinct volumes rotated between steps")
     ap.add_argument("--streams", type=int, default=2,
                     help="volumes in flight (one stream and workspace each)")
@@ -116,6 +225,9 @@ def main(argv=None):
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the moments of one volume "
               "need no collective, and multi-GPU runs are not part of this build", file=sys.stderr)
         return 2
+
+    if a.workload == "serve_mix":
+        return serve_main(a)
 
     import numpy as np
     import torch

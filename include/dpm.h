@@ -229,6 +229,10 @@ int dpm_server_submit(dpm_server *s, const dpm_request *req);
  * the number written, or a negative status. */
 int dpm_server_poll(dpm_server *s, dpm_completion *out, int max, int wait_ms);
 int dpm_server_stats_get(dpm_server *s, dpm_server_stats *out);
+/* Load generator: submits reqs[0..n) in order, each at its t_arrival_ms on the server
+ * clock (sleeping, then spinning for the last 0.2 ms), and returns once all are
+ * submitted (or the first failing submit's status).  Arrival times must not decrease. */
+int dpm_server_replay(dpm_server *s, const dpm_request *reqs, int n);
 /* Waits for every submitted request, then frees the server (completions not yet
  * polled are dropped). */
 int dpm_server_destroy(dpm_server *s);

@@ -250,20 +250,27 @@ class Server:
         return lib().dpm_server_now_ms()
 
     def submit(self, vol, K, t_arrival_ms=0.0):
+        req = self._request(vol, K, t_arrival_ms)
+        rc = lib().dpm_server_submit(self._h, ctypes.byref(req))
+        if rc:
+            self._live.pop(req.tag, None)
+            raise DpmError(rc, "dpm_server_submit")
+        return req.tag
+
+    def _request(self, vol, K, t_arrival_ms):
         import numpy as np
         import torch
         if isinstance(vol, np.ndarray):
             vol = torch.from_numpy(np.ascontiguousarray(vol.view(np.int16) if vol.dtype == np.uint16 else vol))
         if not vol.is_contiguous() or vol.dim() != 3:
             raise ValueError("volume must be a contiguous 3D tensor (N, M, L)")
-        on_dev = vol.is_cuda
         exact = np.zeros((num_moments(min(K, 4)), 2), dtype=np.int64)
         fp = np.zeros(num_moments(K), dtype=np.float64)
         tag = self._next
         self._next += 1
         req = _lib.Request()
         req.data = vol.data_ptr()
-        req.data_on_device = 1 if on_dev else 0
+        req.data_on_device = 1 if vol.is_cuda else 0
         req.dtype = _dtype_code(vol)
         req.dims[:] = [int(vol.shape[2]), int(vol.shape[1]), int(vol.shape[0])]
         req.max_order = int(K)
@@ -271,9 +278,19 @@ class Server:
         req.t_arrival_ms = float(t_arrival_ms)
         req.exact = exact.ctypes.data
         req.fp64 = fp.ctypes.data
-        check(lib().dpm_server_submit(self._h, ctypes.byref(req)), "dpm_server_submit")
         self._live[tag] = (vol, exact, fp, K)
-        return tag
+        return req
+
+    def replay(self, items):
+        """Submit [(vol, K, t_arrival_ms), ...] at their arrival times from a native loop
+        (blocking; run it in a thread and poll meanwhile).  Returns the tags."""
+        reqs = (_lib.Request * len(items))()
+        tags = []
+        for i, (vol, K, t) in enumerate(items):
+            reqs[i] = self._request(vol, K, t)
+            tags.append(reqs[i].tag)
+        check(lib().dpm_server_replay(self._h, reqs, len(items)), "dpm_server_replay")
+        return tags
 
     def poll(self, max_n=256, wait_ms=0):
         """Completed requests: list of dicts with tag, status, batched, times and the Moments."""

@@ -116,6 +116,7 @@ SIGNATURES = {
     "dpm_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Completion), ctypes.c_int, ctypes.c_int]),
     "dpm_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
     "dpm_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "dpm_server_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.c_int]),
 }
 
 _lib = None

@@ -427,6 +427,21 @@ int dpm_server_poll(dpm_server *s, dpm_completion *out, int max, int wait_ms) {
     return n;
 }
 
+int dpm_server_replay(dpm_server *s, const dpm_request *reqs, int n) {
+    if (!s || (!reqs && n > 0) || n < 0) return DPM_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const double t = reqs[i].t_arrival_ms;
+        for (;;) {
+            const double left = t - now_ms_impl();
+            if (left <= 0) break;
+            if (left > 0.2) std::this_thread::sleep_for(std::chrono::microseconds((int64_t)((left - 0.2) * 1000)));
+        }
+        const int rc = dpm_server_submit(s, &reqs[i]);
+        if (rc) return rc;
+    }
+    return DPM_OK;
+}
+
 int dpm_server_stats_get(dpm_server *s, dpm_server_stats *out) {
     if (!s || !out) return DPM_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
