@@ -216,6 +216,8 @@ def main(argv=None):
     ap.add_argument("--hbm-budget", type=int, default=16, help="serve_mix: server arena, GiB")
     ap.add_argument("--server-streams", type=int, default=4, help="serve_mix: server streams")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the run, 3 plain device copies of MIB MiB (calibrates HBM byte counters)")
     ap.add_argument("--nvol", type=int, default=3, help="distinct volumes rotated between steps")
     ap.add_argument("--streams", type=int, default=2,
                     help="volumes in flight (one stream and workspace each)")
@@ -333,6 +335,12 @@ def main(argv=None):
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(V0, K)
     print(json.dumps(out), flush=True)
+    if a.copy_probe:
+        src = torch.empty(a.copy_probe << 20, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     return 0
 
 
