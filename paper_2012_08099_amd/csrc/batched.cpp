@@ -101,6 +101,7 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
         d.M = r.dims[1];
         d.N = r.dims[2];
         d.elem = elem;
+        const int G = lane_voxels(elem);
         const int64_t lanes = (d.L + G - 1) / G;
         if (lanes <= 64) {
             int rr = 8;
@@ -126,7 +127,7 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
         if ((double)vmax * (double)std::max(d.L, d.N) >= 268435456.0) small_p = false;
         // geometry of this ROI's items (full z range): LDS and row layout
         ItemGeom ig;
-        item_geometry(0, nd, d.L, d.N, 0, d.N, ig);
+        item_geometry(0, nd, G, d.L, d.N, 0, d.N, ig);
         p.lds = std::max(p.lds, (size_t)ig.lds_dwords * 4);
         int32_t off = 0, nsl = 0;
         for (int sl = 0; sl < 14; ++sl) {

@@ -205,7 +205,7 @@ int elem_of(dpm_dtype t) { return t == DPM_U8 ? 1 : t == DPM_U16 ? 2 : 0; }
 
 // Lane layout along x for a row of L voxels: sub-rows of R lanes (power of two in
 // [8, 64]) or 64-lane column tiles.
-void lane_layout(int64_t L, int &R, int &CT) {
+void lane_layout(int64_t L, int G, int &R, int &CT) {
     const int64_t lanes = (L + G - 1) / G;
     if (lanes <= 64) {
         int r = 8;
@@ -287,11 +287,12 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
     p.items = (int)(p.M * p.zsplits);
     int rc = plan_widths(p);
     if (rc) return rc;
-    lane_layout(p.L, p.R, p.CT);
+    const int G = lane_voxels(p.elem);
+    lane_layout(p.L, G, p.R, p.CT);
     const int64_t lanes = (p.L + G - 1) / G;
     const bool lanes_exact = (lanes == (int64_t)p.R * p.CT);
     const uintptr_t addr = (uintptr_t)vol_for_alignment;
-    const size_t vec_bytes = p.elem == 2 ? 16 : 8;
+    const size_t vec_bytes = p.elem == 2 ? 16 : 8;  // one lane's load
     p.fast = lanes_exact && (p.L % G == 0) && (p.N % ZALIGN == 0) && (addr % vec_bytes == 0);
     if (const char *e = std::getenv("DPM_FORCE_GENERIC")) {
         if (atoi(e)) p.fast = false;
@@ -311,7 +312,7 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
         for (int s = 0; s < 2; ++s) {
             const int64_t zs0 = firsts[s], ze0 = std::min<int64_t>(zs0 + p.zrows, p.N);
             ItemGeom ig;
-            item_geometry(g, p.gnd[g], p.L, p.N, zs0, ze0, ig);
+            item_geometry(g, p.gnd[g], G, p.L, p.N, zs0, ze0, ig);
             best = std::max(best, (size_t)ig.lds_dwords * 4);
             for (int i = 0; i < p.gnd[g]; ++i)
                 for (int side = 0; side < 2; ++side)

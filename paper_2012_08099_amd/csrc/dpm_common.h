@@ -35,31 +35,32 @@ __host__ __device__ constexpr int iabs_c(int v) { return v < 0 ? -v : v; }
 __host__ __device__ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
 
 // Voxels per lane along x: one 16-byte load (uint16) or 8-byte load (uint8).
-constexpr int G = 8;
+__host__ __device__ constexpr int lane_voxels(int elem) { return 8; }
 
 // LDS padding period of a row accumulator: one pad dword per PP bins.  Lanes of a
-// sub-row flush windows at a stride of alpha*G bins, i.e. 9*alpha padded dwords: odd
-// (conflict-free) for alpha = 1, 3 and two-way for alpha = 2.
-__host__ __device__ constexpr int dir_pp(int d) { return 8; }
+// sub-row flush windows at a stride of alpha*G bins; the padded stride is odd
+// (conflict-free) except for alpha = 2 with G = 8, which stays two-way so that its
+// window blocks stay 8 rows long.
+__host__ __device__ constexpr int dir_pp(int d, int G) { return (G == 4 && dir_alpha(d) == 2) ? 8 : G; }
 // Rows per window block: the smallest T with beta*T = 0 mod PP, so every block base
 // is PP-aligned relative to the row origin and flush offsets are compile-time.
-__host__ __device__ constexpr int dir_td(int d) {
-    return dir_beta(d) == 0 ? 1 : dir_pp(d) / gcd_c(iabs_c(dir_beta(d)), dir_pp(d));
+__host__ __device__ constexpr int dir_td(int d, int G) {
+    return dir_beta(d) == 0 ? 1 : dir_pp(d, G) / gcd_c(iabs_c(dir_beta(d)), dir_pp(d, G));
 }
 // Window slots of one lane per block: alpha (G-1) + |beta| (T_d - 1) + 1.
-__host__ __device__ constexpr int dir_slots(int d) {
-    return dir_alpha(d) * (G - 1) + iabs_c(dir_beta(d)) * (dir_td(d) - 1) + 1;
+__host__ __device__ constexpr int dir_slots(int d, int G) {
+    return dir_alpha(d) * (G - 1) + iabs_c(dir_beta(d)) * (dir_td(d, G) - 1) + 1;
 }
 // Slot shift that keeps slots non-negative for beta < 0.
-__host__ __device__ constexpr int dir_shift(int d) {
-    return dir_beta(d) < 0 ? iabs_c(dir_beta(d)) * (dir_td(d) - 1) : 0;
+__host__ __device__ constexpr int dir_shift(int d, int G) {
+    return dir_beta(d) < 0 ? iabs_c(dir_beta(d)) * (dir_td(d, G) - 1) : 0;
 }
 
 // Direction groups: each is one launch of the projection kernel (register budget).
 constexpr int NGROUP = 3;
 __host__ __device__ constexpr int group_begin(int g) { return g == 0 ? 0 : g == 1 ? 7 : 12; }
 __host__ __device__ constexpr int group_end(int g) { return g == 0 ? 7 : g == 1 ? 12 : 17; }
-// Rows per chunk (unit of work and of double buffering) = lcm of the group's T_d.
+// Rows per chunk (unit of work and of double buffering): a multiple of every T_d.
 __host__ __device__ constexpr int group_rows(int g) { return 8; }
 // Copies of the (0,1) row accumulator: 8-lane groups g and g+4 of a wave share copy g % 4.
 constexpr int YZ_COPIES = 4;
@@ -105,8 +106,9 @@ struct ItemGeom {
 
 DPM_HD int64_t padded(int64_t u, int pp) { return u + u / pp; }
 
-// Geometry of direction i of group g for rows [zs, ze) (no LDS offset yet).
-DPM_HD void dir_geometry(int g, int i, int64_t L, int64_t N, int64_t zs, int64_t ze, DirGeom &dg,
+// Geometry of direction i of group g for rows [zs, ze) and G voxels per lane (no LDS
+// offset yet).
+DPM_HD void dir_geometry(int g, int i, int G, int64_t L, int64_t N, int64_t zs, int64_t ze, DirGeom &dg,
                          int32_t &alo_neg, int32_t &ahi_neg, int32_t &alo_pos, int32_t &ahi_pos) {
     const int T = group_rows(g);
     const int64_t Xp = (L + G - 1) / G * G;    // padded x extent
@@ -136,7 +138,7 @@ DPM_HD void dir_geometry(int g, int i, int64_t L, int64_t N, int64_t zs, int64_t
     dg.lo = (int32_t)bmin;
     dg.rb_lo = (int32_t)rlo;
     dg.rb_hi = (int32_t)rhi;
-    dg.lds_len = d == 1 ? (int32_t)(YZ_COPIES * ((nch * T) | 1)) : (int32_t)(padded(bmax - bmin, dir_pp(d)) + 1);
+    dg.lds_len = d == 1 ? (int32_t)(YZ_COPIES * ((nch * T) | 1)) : (int32_t)(padded(bmax - bmin, dir_pp(d, G)) + 1);
     // sides: negative [rlo, min(rhi, o-1)], non-negative [max(rlo, o), rhi]
     const int64_t n1 = rhi < o - 1 ? rhi : o - 1;
     const int64_t p0 = rlo > o ? rlo : o;
@@ -155,7 +157,7 @@ DPM_HD void dir_geometry(int g, int i, int64_t L, int64_t N, int64_t zs, int64_t
 }
 
 // Whole-item geometry (host, and device for batched items).
-DPM_HD void item_geometry(int g, int nd, int64_t L, int64_t N, int64_t zs, int64_t ze, ItemGeom &ig) {
+DPM_HD void item_geometry(int g, int nd, int G, int64_t L, int64_t N, int64_t zs, int64_t ze, ItemGeom &ig) {
     const int T = group_rows(g);
     const int64_t nch = (ze - zs + T - 1) / T;
     int32_t off = 0;
@@ -169,7 +171,7 @@ DPM_HD void item_geometry(int g, int nd, int64_t L, int64_t N, int64_t zs, int64
             continue;
         }
         DirGeom &dg = ig.dir[i];
-        dir_geometry(g, i, L, N, zs, ze, dg, ig.seg_alo[2 * i], ig.seg_ahi[2 * i], ig.seg_alo[2 * i + 1],
+        dir_geometry(g, i, G, L, N, zs, ze, dg, ig.seg_alo[2 * i], ig.seg_ahi[2 * i], ig.seg_alo[2 * i + 1],
                      ig.seg_ahi[2 * i + 1]);
         dg.lds_off = off;
         if (group_begin(g) + i == 1) {

@@ -7,7 +7,8 @@
 
 namespace dpm {
 
-constexpr int SLICE_WAVES = 4;  // waves per projection workgroup
+// waves per projection workgroup
+__host__ __device__ constexpr int slice_waves(int elem) { return 4; }
 constexpr int NLR_MAX = 12;     // widest 2D-moment / recombination integer (32-bit limbs)
 
 // Exact power sums on the matrix cores: the row values P(a) and the powers a^k are

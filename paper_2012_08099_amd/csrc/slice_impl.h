@@ -7,8 +7,8 @@
 // negative-index image at column N-1 (the offset correction of Section 5).
 //
 // Projection mapping (gfx950, wave64): a sub-row of R lanes covers one volume row, lane
-// r owning the G = 8 consecutive voxels x0 = 64*G*ct + G*r .. x0+7 (one 16- or 8-byte
-// non-temporal load).  Each sub-row walks a contiguous range of 8-row units (z), loads
+// r owning the G = 8 consecutive voxels x0 = 64*G*ct + G*r .. x0+G-1, one 16-byte
+// (uint16) or 8-byte (uint8) non-temporal load.  Each sub-row walks a contiguous range of 8-row units (z), loads
 // of the next unit in flight while the current one is summed.  Per voxel and direction
 // there is one integer add into a register window; windows are flushed to LDS row
 // accumulators every T_d rows with ds_add at compile-time offsets.  The (0,1) direction
@@ -33,45 +33,48 @@ struct StaticFor {
     }
 };
 
+// One lane's voxels of one row: G = lane_voxels(elem) voxels, one 16-byte (uint16) or
+// 8-byte (uint8) load.
 template <typename VT>
 struct VecOf;
 template <>
 struct VecOf<uint16_t> {
-    using type = uint4;  // 8 voxels
+    using type = uint4;
     typedef unsigned int raw __attribute__((ext_vector_type(4)));
+    static constexpr int G = lane_voxels(2);
 };
 template <>
 struct VecOf<uint8_t> {
-    using type = uint2;  // 8 voxels
+    using type = uint2;
     typedef unsigned int raw __attribute__((ext_vector_type(2)));
+    static constexpr int G = lane_voxels(1);
 };
 
 template <typename VT>
-__device__ __forceinline__ uint32_t voxel(const typename VecOf<VT>::type &v, int j);
-template <>
-__device__ __forceinline__ uint32_t voxel<uint16_t>(const uint4 &v, int j) {
-    const uint32_t w = j < 2 ? v.x : j < 4 ? v.y : j < 6 ? v.z : v.w;
-    return (j & 1) ? (w >> 16) : (w & 0xffffu);
-}
-template <>
-__device__ __forceinline__ uint32_t voxel<uint8_t>(const uint2 &v, int j) {
-    const uint32_t w = j < 4 ? v.x : v.y;
-    return (w >> (8 * (j & 3))) & 0xffu;
+__device__ __forceinline__ uint32_t voxel(const typename VecOf<VT>::type &v, int j) {
+    if constexpr (sizeof(VT) == 2) {
+        const uint32_t w = j < 2 ? v.x : j < 4 ? v.y : j < 6 ? v.z : v.w;
+        return (j & 1) ? (w >> 16) : (w & 0xffffu);
+    } else {
+        const uint32_t w = j < 4 ? v.x : v.y;
+        return (w >> (8 * (j & 3))) & 0xffu;
+    }
 }
 
-// sum of the 8 voxels of a lane
-__device__ __forceinline__ uint32_t lane_sum(const uint4 &v) {
-    typedef unsigned short us2 __attribute__((ext_vector_type(2)));
-    const us2 one = {1, 1};
-    uint32_t s = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v.x), one, 0u, false);
-    s = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v.y), one, s, false);
-    s = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v.z), one, s, false);
-    s = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v.w), one, s, false);
-    return s;
-}
-__device__ __forceinline__ uint32_t lane_sum(const uint2 &v) {
-    uint32_t s = __builtin_amdgcn_udot4(v.x, 0x01010101u, 0u, false);
-    return __builtin_amdgcn_udot4(v.y, 0x01010101u, s, false);
+// sum of the voxels of a lane
+template <typename VT>
+__device__ __forceinline__ uint32_t lane_sum(const typename VecOf<VT>::type &v) {
+    if constexpr (sizeof(VT) == 2) {
+        typedef unsigned short us2 __attribute__((ext_vector_type(2)));
+        const us2 one = {1, 1};
+        uint32_t s = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v.x), one, 0u, false);
+        s = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v.y), one, s, false);
+        s = __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v.z), one, s, false);
+        return __builtin_amdgcn_udot2(__builtin_bit_cast(us2, v.w), one, s, false);
+    } else {
+        const uint32_t s = __builtin_amdgcn_udot4(v.x, 0x01010101u, 0u, false);
+        return __builtin_amdgcn_udot4(v.y, 0x01010101u, s, false);
+    }
 }
 
 // Sum over each aligned group of 8 lanes; every lane of the group gets the total.
@@ -83,9 +86,9 @@ __device__ __forceinline__ uint32_t group8_sum(uint32_t s) {
 }
 
 // Is (tt, j) the first touch of its window slot within a block (t outer, j inner)?
-template <int D>
+template <int D, int G>
 __device__ constexpr bool first_touch(int tt, int j) {
-    const int A = dir_alpha(D), Bt = dir_beta(D), SH = dir_shift(D);
+    const int A = dir_alpha(D), Bt = dir_beta(D), SH = dir_shift(D, G);
     const int s = A * j + Bt * tt + SH;
     for (int t2 = 0; t2 <= tt; ++t2)
         for (int j2 = 0; j2 < G; ++j2) {
@@ -97,20 +100,20 @@ __device__ constexpr bool first_touch(int tt, int j) {
 
 // Does any voxel of a block land in window slot s?  (alpha j + beta t hits every slot
 // only when alpha or |beta| is 1; e.g. (3,2) never reaches slot 1.)
-template <int D>
+template <int D, int G>
 __device__ constexpr bool slot_used(int s) {
-    const int A = dir_alpha(D), Bt = dir_beta(D), SH = dir_shift(D);
-    for (int t2 = 0; t2 < dir_td(D); ++t2)
+    const int A = dir_alpha(D), Bt = dir_beta(D), SH = dir_shift(D, G);
+    for (int t2 = 0; t2 < dir_td(D, G); ++t2)
         for (int j2 = 0; j2 < G; ++j2)
             if (A * j2 + Bt * t2 + SH == s) return true;
     return false;
 }
 
 template <typename VT, bool FAST>
-__device__ __forceinline__ typename VecOf<VT>::type load_lane(const VT *row, int64_t x0, int64_t L,
-                                                              bool in) {
+__device__ __forceinline__ typename VecOf<VT>::type load_lane(const VT *row, int64_t x0, int64_t L, bool in) {
     using Vec = typename VecOf<VT>::type;
     using Raw = typename VecOf<VT>::raw;
+    constexpr int G = VecOf<VT>::G;
     Vec v{};
     if constexpr (FAST) {
         // streamed once: non-temporal, so it does not evict the small shared tables
@@ -144,8 +147,9 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
                              int64_t ze, int R, int CT, uint32_t *lds, const ItemGeom &ig) {
     using Tr = GroupTraits<D0, ND>;
     using Vec = typename VecOf<VT>::type;
+    constexpr int G = VecOf<VT>::G;
     constexpr int T = Tr::T;
-    constexpr int NW = SLICE_WAVES;
+    constexpr int NW = slice_waves((int)sizeof(VT));
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int SR = 64 / R;
@@ -163,7 +167,7 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
     int32_t cbase[ND], coff[ND];
     StaticFor<0, ND>::run([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        cbase[i] = (int32_t)(ig.dir[i].o - dir_shift(D0 + i) - ig.dir[i].lo);
+        cbase[i] = (int32_t)(ig.dir[i].o - dir_shift(D0 + i, G) - ig.dir[i].lo);
         coff[i] = ig.dir[i].lds_off;
     });
     const int32_t yz_off = ig.yz_off, yz_stride = ig.yz_stride;
@@ -223,7 +227,7 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
                     xy[j] += voxel<VT>(v, j);
                 });
             }
-            if constexpr (Tr::has_yz) yzs[t] = group8_sum(lane_sum(v));
+            if constexpr (Tr::has_yz) yzs[t] = group8_sum(lane_sum<VT>(v));
         });
 
         // sheared directions: register windows, flushed every T_d rows
@@ -231,8 +235,8 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
             constexpr int i = decltype(ic)::value;
             constexpr int d = D0 + i;
             if constexpr (d >= 2) {
-                constexpr int A = dir_alpha(d), Bt = dir_beta(d), TD = dir_td(d);
-                constexpr int S = dir_slots(d), SH = dir_shift(d), PP = dir_pp(d);
+                constexpr int A = dir_alpha(d), Bt = dir_beta(d), TD = dir_td(d, G);
+                constexpr int S = dir_slots(d, G), SH = dir_shift(d, G), PP = dir_pp(d, G);
                 // lane base in bins relative to the LDS row origin (32-bit: bins < 2^31)
                 const int32_t rel0 = (int32_t)(A * x0 + Bt * zc0) + cbase[i];
                 const int32_t doff = coff[i];
@@ -244,7 +248,7 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
                     StaticFor<0, G>::run([&](auto jc) {
                         constexpr int j = decltype(jc)::value;
                         constexpr int s = A * j + Bt * tt + SH;
-                        if constexpr (first_touch<d>(tt, j)) w[s] = voxel<VT>(v, j);
+                        if constexpr (first_touch<d, G>(tt, j)) w[s] = voxel<VT>(v, j);
                         else w[s] += voxel<VT>(v, j);
                     });
                     if constexpr (tt == TD - 1) {
@@ -253,7 +257,7 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
                             uint32_t *base = lds + doff + (lb + lb / PP);
                             StaticFor<0, S>::run([&](auto sc) {
                                 constexpr int s = decltype(sc)::value;
-                                if constexpr (slot_used<d>(s)) atomicAdd(base + (s + s / PP), w[s]);
+                                if constexpr (slot_used<d, G>(s)) atomicAdd(base + (s + s / PP), w[s]);
                             });
                         }
                     }
@@ -276,7 +280,7 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
             if (last_in_tile) {
                 if (FAST || valid) {
                     const uint32_t x0u = (uint32_t)x0;
-                    uint32_t *base = lds + coff[0] + (x0u + x0u / 8);
+                    uint32_t *base = lds + coff[0] + (x0u + x0u / (uint32_t)dir_pp(0, G));
                     StaticFor<0, G>::run([&](auto jc) {
                         constexpr int j = decltype(jc)::value;
                         atomicAdd(base + j, xy[j]);
@@ -315,10 +319,13 @@ struct SegView {
     int32_t neg;          // 1: a = o - bin, 0: a = bin - o
     int32_t yz;           // 1: (0,1) image, sum of the copies
     int32_t yz_stride;
+    int32_t pp;           // LDS padding period of the row
 };
 
-__device__ __forceinline__ SegView seg_view(const uint32_t *lds, const ItemGeom &ig, int i, int side, bool yz) {
+__device__ __forceinline__ SegView seg_view(const uint32_t *lds, const ItemGeom &ig, int i, int side, bool yz,
+                                            int pp) {
     SegView v;
+    v.pp = pp;
     v.neg = side == 0;
     v.alo = ig.seg_alo[2 * i + side];
     v.ahi = ig.seg_ahi[2 * i + side];
@@ -340,7 +347,7 @@ __device__ __forceinline__ uint32_t seg_value(const SegView &v, int32_t a) {
         for (int c = 0; c < YZ_COPIES; ++c) s += v.row[u + c * v.yz_stride];
         return s;
     }
-    return v.row[u + u / 8];
+    return v.row[u + u / (uint32_t)v.pp];
 }
 
 // ------------------------------------------------------------ per-item driver
@@ -351,14 +358,14 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
                            int32_t *__restrict__ img, const int64_t *img_off, const int64_t *img_w,
                            uint32_t *lds, ItemGeom &ig) {
     using Tr = GroupTraits<D0, ND>;
-    constexpr int NW = SLICE_WAVES;
+    constexpr int NW = slice_waves((int)sizeof(VT));
     const int tid = threadIdx.x;
 
     // geometry: one thread per direction, then the LDS offsets
     if (tid < ND) {
         DirGeom dg;
         int32_t an, hn, ap, hp;
-        dir_geometry(Tr::g, tid, L, N, zs, ze, dg, an, hn, ap, hp);
+        dir_geometry(Tr::g, tid, VecOf<VT>::G, L, N, zs, ze, dg, an, hn, ap, hp);
         ig.dir[tid] = dg;
         ig.seg_alo[2 * tid] = an;
         ig.seg_ahi[2 * tid] = hn;
@@ -392,7 +399,8 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
         StaticFor<0, ND>::run([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             const int64_t lo = ig.dir[i].rb_lo, hi = ig.dir[i].rb_hi, o = ig.dir[i].o;
-            const SegView vn = seg_view(lds, ig, i, 0, D0 + i == 1), vp = seg_view(lds, ig, i, 1, D0 + i == 1);
+            constexpr int pp = dir_pp(D0 + i, VecOf<VT>::G);
+            const SegView vn = seg_view(lds, ig, i, 0, D0 + i == 1, pp), vp = seg_view(lds, ig, i, 1, D0 + i == 1, pp);
             int32_t *row = img + img_off[i] + y * img_w[i];
             for (int64_t b = lo + tid; b <= hi; b += NW * 64)
                 row[b] = (int32_t)(b < o ? seg_value(vn, (int32_t)(o - b)) : seg_value(vp, (int32_t)(b - o)));
@@ -408,7 +416,7 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
             const int s = 2 * d + side;
             const int32_t len = slot_len[s];
             if (len == 0) continue;
-            const SegView v = seg_view(lds, ig, i, side, d == 1);
+            const SegView v = seg_view(lds, ig, i, side, d == 1, dir_pp(d, VecOf<VT>::G));
             // 16-byte stores: len is a multiple of 64 and the rows are 256-byte aligned
             int4 *dst = reinterpret_cast<int4 *>(rows_out + slot_off[s]);
             for (int32_t a = 4 * tid; a < len; a += 4 * NW * 64) {
@@ -424,7 +432,7 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
 
 // ------------------------------------------------------------ kernels
 template <typename VT, int D0, int ND, bool FAST>
-__global__ void __launch_bounds__(SLICE_WAVES * 64)
+__global__ void __launch_bounds__(slice_waves((int)sizeof(VT)) * 64)
 slice_kernel(SliceArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ ItemGeom ig;
@@ -438,7 +446,7 @@ slice_kernel(SliceArgs a) {
 }
 
 template <typename VT, int D0, int ND>
-__global__ void __launch_bounds__(SLICE_WAVES * 64)
+__global__ void __launch_bounds__(slice_waves((int)sizeof(VT)) * 64)
 slice_batched_kernel(BatchSliceArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ ItemGeom ig;
@@ -460,7 +468,7 @@ hipError_t launch_one(const SliceArgs &a, int items, size_t lds, hipStream_t st)
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, dim3(items), dim3(SLICE_WAVES * 64), lds, st, a);
+    hipLaunchKernelGGL(k, dim3(items), dim3(slice_waves((int)sizeof(VT)) * 64), lds, st, a);
     return hipGetLastError();
 }
 
@@ -489,7 +497,7 @@ hipError_t launch_b_one(const BatchSliceArgs &a, int items, size_t lds, hipStrea
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, dim3(items), dim3(SLICE_WAVES * 64), lds, st, a);
+    hipLaunchKernelGGL(k, dim3(items), dim3(slice_waves((int)sizeof(VT)) * 64), lds, st, a);
     return hipGetLastError();
 }
 
