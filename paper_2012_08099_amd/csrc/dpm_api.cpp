@@ -181,6 +181,7 @@ struct Plan {
     int zsplits = 1, zrows = 0, items = 0;
     int R = 8, CT = 1;
     bool fast = false;
+    bool chain = false;  // chained-window projection (first group)
     int nls = 4, nlr = 4;
     int ngroups = 0;
     int gnd[NGROUP] = {};
@@ -297,6 +298,12 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
     if (const char *e = std::getenv("DPM_FORCE_GENERIC")) {
         if (atoi(e)) p.fast = false;
     }
+    // chained-window projection: opt-in (it is exact, but measured slower than the
+    // windowed kernel on the 512^3 workload)
+    p.chain = false;
+    if (const char *e = std::getenv("DPM_CHAIN")) {
+        if (atoi(e)) p.chain = p.fast && p.elem == 2 && p.R == 64 && p.zrows % 32 == 0 && p.N % 32 == 0;
+    }
     p.npairs = n_pairs(K);
     // groups, LDS per group and the row layout (the first item is the largest; the
     // last one may differ)
@@ -411,7 +418,7 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
             a.img_off[i] = (images && i < p.gnd[g]) ? img_off[group_begin(g) + i] : 0;
             a.img_w[i] = (images && i < p.gnd[g]) ? img_w[group_begin(g) + i] : 0;
         }
-        hipError_t e = launch_slice(p.elem, p.fast, g, p.gnd[g], a, p.items, p.lds[g], st);
+        hipError_t e = launch_slice(p.elem, p.fast, p.chain && g == 0, g, p.gnd[g], a, p.items, p.lds[g], st);
         if (e != hipSuccess) return hip_fail(e);
     }
     if (!moments) return DPM_OK;

@@ -64,6 +64,9 @@ __host__ __device__ constexpr int group_end(int g) { return g == 0 ? 7 : g == 1 
 __host__ __device__ constexpr int group_rows(int g) { return 8; }
 // Copies of the (0,1) row accumulator: 8-lane groups g and g+4 of a wave share copy g % 4.
 constexpr int YZ_COPIES = 4;
+// Dwords after the row accumulators that absorb the (0,1) adds of the lanes that hold
+// no group sum (lane + row offset < 96), so that add needs no branch.
+constexpr int LDS_SINK = 96;
 constexpr int ZALIGN = 16;  // z-split boundaries are multiples of every group's chunk
 
 __host__ __device__ constexpr int n_moments(int K) { return (K + 1) * (K + 2) * (K + 3) / 6; }
@@ -101,7 +104,7 @@ struct ItemGeom {
     int32_t yz_off;     // dword offset of the (0,1) accumulator copies
     int32_t yz_stride;  // dwords between copies (odd)
     int32_t n_chunks;   // chunks of group_rows() rows in [zs, ze)
-    int32_t lds_dwords; // projection part of LDS
+    int32_t lds_dwords; // projection part of LDS (row accumulators + sink)
 };
 
 DPM_HD int64_t padded(int64_t u, int pp) { return u + u / pp; }
@@ -180,7 +183,7 @@ DPM_HD void item_geometry(int g, int nd, int G, int64_t L, int64_t N, int64_t zs
         }
         off += dg.lds_len;
     }
-    ig.lds_dwords = off;
+    ig.lds_dwords = off + LDS_SINK;
 }
 
 // Row storage of the power-sum input: segment slot s of every item holds `len` int32

@@ -92,7 +92,9 @@ struct PowerArgs {
 };
 hipError_t launch_power(int nls, int nlr, const PowerArgs &a, hipStream_t st);
 
-hipError_t launch_slice(int elem, bool fast, int g, int nd, const SliceArgs &a, int items, size_t lds,
+// chain: the chained-window variant (uint16, first group, whole 64-lane rows, z ranges
+// that are whole 32-row units)
+hipError_t launch_slice(int elem, bool fast, bool chain, int g, int nd, const SliceArgs &a, int items, size_t lds,
                         hipStream_t st);
 hipError_t launch_slice_batched(int elem, int g, int nd, const BatchSliceArgs &a, int items, size_t lds,
                                 hipStream_t st);

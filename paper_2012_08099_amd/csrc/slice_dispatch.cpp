@@ -4,6 +4,7 @@
 namespace dpm {
 #define DECL(name) hipError_t name(int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st);
 DECL(launch_slice_g0_u16_fast)
+DECL(launch_slice_g0_u16_chain)
 DECL(launch_slice_g0_u16_gen)
 DECL(launch_slice_g0_u8_fast)
 DECL(launch_slice_g0_u8_gen)
@@ -13,9 +14,10 @@ hipError_t launch_slice_g12_u16(int g, bool fast, int nd, const SliceArgs &a, in
 hipError_t launch_slice_g12_u8(int g, bool fast, int nd, const SliceArgs &a, int items, size_t lds,
                                hipStream_t st);
 
-hipError_t launch_slice(int elem, bool fast, int g, int nd, const SliceArgs &a, int items, size_t lds,
+hipError_t launch_slice(int elem, bool fast, bool chain, int g, int nd, const SliceArgs &a, int items, size_t lds,
                         hipStream_t st) {
     if (g == 0) {
+        if (elem == 2 && chain) return launch_slice_g0_u16_chain(nd, a, items, lds, st);
         if (elem == 2) return fast ? launch_slice_g0_u16_fast(nd, a, items, lds, st)
                                    : launch_slice_g0_u16_gen(nd, a, items, lds, st);
         return fast ? launch_slice_g0_u8_fast(nd, a, items, lds, st) : launch_slice_g0_u8_gen(nd, a, items, lds, st);

@@ -133,6 +133,12 @@ __device__ __forceinline__ typename VecOf<VT>::type load_lane(const VT *row, int
     return v;
 }
 
+template <int ND>
+struct Tr0 {
+    static constexpr bool has_xy = true;
+    static constexpr bool has_yz = ND >= 2;
+};
+
 template <int D0, int ND>
 struct GroupTraits {
     static constexpr int g = D0 == 0 ? 0 : D0 == 7 ? 1 : 2;
@@ -309,6 +315,270 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
     }
 }
 
+// ------------------------------------------------------------ step 1, chained windows
+// Variant for whole 64-lane rows (R = 64) of the first direction group, P-row units.
+// For direction (alpha, beta) a lane's voxels of one row fall in alpha (G-1) + 1 bins
+// that move by beta per row; the lane keeps them in a ring of W = alpha G registers
+// (bin mod W).  When the window has moved past a bin, the lane hands the bin's partial
+// sum to the neighbouring lane whose window reaches it next (DPP wave shift): that bin
+// lands in the neighbour's ring slot it is vacating at the same moment (W = alpha G), so
+// the hand-over is one register move.  Each sum travels down the lanes collecting every
+// contribution of the wave; only the lane at the end of the chain (lane 0 for beta > 0,
+// lane 63 for beta < 0) holds finished bins, and it shifts them into a lane-spread
+// register that is written to LDS once per unit (one ds_add of P lanes).
+constexpr int CH_P = 32;     // rows per unit
+constexpr int CH_LA = 16;    // row slots per lane (loads run LA - 1 rows ahead)
+constexpr int CH_WAVES = 4;  // waves per workgroup (about 207 registers: 2 waves per SIMD)
+
+__device__ constexpr int chain_ring(int d) { return dir_alpha(d) * 8; }
+
+template <int D0, int I>
+__device__ constexpr int chain_off() {
+    int o = 0;
+    for (int i = 0; i < I; ++i)
+        if (D0 + i >= 2) o += chain_ring(D0 + i);
+    return o;
+}
+template <int D0, int I>
+__device__ constexpr int chain_eoff() {
+    int o = 0;
+    for (int i = 0; i < I; ++i)
+        if (D0 + i >= 2) o += iabs_c(dir_beta(D0 + i));
+    return o;
+}
+
+// Which bin (relative to the unit's frame) ring slot s holds after the last row of a
+// unit, in steady state; CH_NONE if none.  Simulates two units of the schedule: adds
+// of each row, then the hand-over of the bins the next row cannot reach (the slot
+// receives the neighbour's bin, alpha G further along).  CH_BAD flags an add into a
+// slot holding another bin (the chain reasoning would be wrong).
+constexpr int CH_NONE = -1000000, CH_BAD = -2000000;
+template <int D>
+__device__ constexpr int chain_slot_bin(int s) {
+    constexpr int A = dir_alpha(D), B = dir_beta(D), AB = B < 0 ? -B : B, W = chain_ring(D), P = CH_P;
+    int bin[64] = {};
+    bool has[64] = {};
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1)
+            for (int k = 0; k < W; ++k)
+                if (has[k]) bin[k] += B > 0 ? -B * P : AB * P;
+        for (int t = 0; t < P; ++t) {
+            const int vt = B > 0 ? B * t : AB * (P - 1 - t);
+            for (int j = 0; j < 8; ++j) {
+                const int v = A * j + vt, sl = v % W;
+                if (has[sl] && bin[sl] != v) return CH_BAD;
+                has[sl] = true;
+                bin[sl] = v;
+            }
+            const int r0 = B > 0 ? vt : vt + A * 7 - AB + 1;
+            for (int k = 0; k < AB; ++k) {
+                const int v = r0 + k, sl = v % W;
+                if (!has[sl] || bin[sl] != v) return CH_BAD;
+                bin[sl] = v + (B > 0 ? A * 8 : -A * 8);
+            }
+        }
+    }
+    return has[s] ? bin[s] : CH_NONE;
+}
+template <int D>
+__device__ constexpr bool chain_ok() {
+    for (int s = 0; s < chain_ring(D); ++s)
+        if (chain_slot_bin<D>(s) == CH_BAD) return false;
+    return true;
+}
+
+template <typename VT, int ND>
+__device__ void project_rows_chain(const VT *__restrict__ slice, int64_t L, int64_t pitch_z, int64_t zs,
+                                   int64_t ze, int CT, uint32_t *lds, const ItemGeom &ig) {
+    using Vec = typename VecOf<VT>::type;
+    constexpr int G = VecOf<VT>::G;
+    static_assert(G == 8, "chained windows assume 8 voxels per lane");
+    constexpr int P = CH_P, LA = CH_LA;
+    constexpr int NRING = chain_off<0, ND>(), NE = chain_eoff<0, ND>();
+    constexpr int NW = CH_WAVES;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int32_t nper = (int32_t)((ze - zs) / P);  // caller guarantees (ze - zs) % P == 0
+    const int32_t U = CT * nper;
+    const int32_t u_begin = (int32_t)((int64_t)wave * U / NW), u_end = (int32_t)((int64_t)(wave + 1) * U / NW);
+    if (u_begin >= u_end) return;
+    const int32_t Z = nper * P;
+
+    int32_t dlo[ND], doff[ND];
+    StaticFor<0, ND>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        dlo[i] = __builtin_amdgcn_readfirstlane(ig.dir[i].o - ig.dir[i].lo);
+        doff[i] = __builtin_amdgcn_readfirstlane(ig.dir[i].lds_off);
+    });
+    const int32_t yz_off = __builtin_amdgcn_readfirstlane(ig.yz_off);
+    const int32_t yz_stride = __builtin_amdgcn_readfirstlane(ig.yz_stride);
+    const int32_t sink = __builtin_amdgcn_readfirstlane(ig.lds_dwords) - LDS_SINK;
+
+    uint32_t xy[G];
+    uint32_t ring[NRING > 0 ? NRING : 1];
+    uint32_t ebuf[NE > 0 ? NE : 1];
+#pragma unroll
+    for (int j = 0; j < G; ++j) xy[j] = 0u;
+#pragma unroll
+    for (int k = 0; k < NRING; ++k) ring[k] = 0u;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) ebuf[k] = 0u;
+
+    auto unit_base = [&](int32_t ct, int32_t per) -> const VT * {
+        return slice + (zs + (int64_t)per * P) * pitch_z + ((int64_t)ct * 64 * G + (int64_t)lane * G);
+    };
+    auto pin = [&]() {
+#pragma unroll
+        for (int j = 0; j < G; ++j) asm volatile("" : "+v"(xy[j]));
+#pragma unroll
+        for (int k = 0; k < NRING; ++k) asm volatile("" : "+v"(ring[k]));
+    };
+
+    int32_t ct = u_begin / nper, per = u_begin - ct * nper;
+    const VT *cb = unit_base(ct, per);
+    Vec dbuf[LA];
+    StaticFor<0, LA>::run([&](auto tc) {
+        constexpr int t = decltype(tc)::value;
+        dbuf[t] = load_lane<VT, true>(cb + (int64_t)t * pitch_z, 0, L, true);
+        __builtin_amdgcn_sched_barrier(0);
+    });
+
+    auto unit = [&](auto more_c) {
+        constexpr bool more = decltype(more_c)::value;
+        int32_t ct2 = ct, per2 = per + 1;
+        if (per2 == nper) {
+            per2 = 0;
+            ++ct2;
+        }
+        const VT *nb = more ? unit_base(ct2, per2) : cb;
+        const bool seg_end = !more || ct2 != ct;
+        const int32_t x0 = ct * 64 * G + lane * G;
+        const int32_t zrel0 = per * P;
+        const int32_t yzb = (lane & 7) == 0 ? yz_off + ((lane >> 3) & (YZ_COPIES - 1)) * yz_stride + zrel0
+                                            : sink + lane;
+        // frame of each ring: U0 = alpha x0 + beta z_frame + o - lo, z_frame = first
+        // (beta > 0) or last (beta < 0) row of the unit
+        int32_t u0[ND];
+        StaticFor<0, ND>::run([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int d = i;
+            if constexpr (d >= 2) {
+                constexpr int A = dir_alpha(d), B = dir_beta(d);
+                const int32_t zf = (int32_t)zs + zrel0 + (B < 0 ? P - 1 : 0);
+                u0[i] = A * x0 + B * zf + dlo[i];
+            }
+        });
+
+        StaticFor<0, P>::run([&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            const Vec v = dbuf[t % LA];
+            if constexpr (Tr0<ND>::has_xy) {
+                StaticFor<0, G>::run([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    xy[j] += voxel<VT>(v, j);
+                });
+            }
+            if constexpr (Tr0<ND>::has_yz) atomicAdd(lds + yzb + t, group8_sum(lane_sum<VT>(v)));
+            StaticFor<0, ND>::run([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int d = i;
+                if constexpr (d >= 2) {
+                    constexpr int A = dir_alpha(d), B = dir_beta(d), AB = B < 0 ? -B : B;
+                    constexpr int W = chain_ring(d), RO = chain_off<0, i>(), EO = chain_eoff<0, i>();
+                    constexpr int vt = B > 0 ? B * t : AB * (P - 1 - t);
+                    StaticFor<0, G>::run([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        ring[RO + (A * j + vt) % W] += voxel<VT>(v, j);
+                    });
+                    // bins the next row cannot reach: hand them along the chain
+                    constexpr int r0 = B > 0 ? vt : vt + A * (G - 1) - AB + 1;
+                    StaticFor<0, AB>::run([&](auto kc) {
+                        constexpr int k = decltype(kc)::value;
+                        constexpr int sl = RO + (r0 + k) % W;
+                        if constexpr (B > 0) {
+                            // end lane 0 keeps its finished bin; lane l passes to l - 1
+                            ebuf[EO + k] = (uint32_t)__builtin_amdgcn_update_dpp((int)ring[sl], (int)ebuf[EO + k],
+                                                                                 0x138, 0xF, 0xF, false);
+                            ring[sl] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)ring[sl], 0x130, 0xF, 0xF, true);
+                        } else {
+                            ebuf[EO + k] = (uint32_t)__builtin_amdgcn_update_dpp((int)ring[sl], (int)ebuf[EO + k],
+                                                                                 0x130, 0xF, 0xF, false);
+                            ring[sl] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)ring[sl], 0x138, 0xF, 0xF, true);
+                        }
+                    });
+                }
+            });
+            if constexpr (t % 2 == 1) pin();
+            if constexpr (t + LA < P) dbuf[t % LA] = load_lane<VT, true>(cb + (int64_t)(t + LA) * pitch_z, 0, L, true);
+            else if constexpr (more) dbuf[t % LA] = load_lane<VT, true>(nb + (int64_t)(t + LA - P) * pitch_z, 0, L, true);
+            __builtin_amdgcn_sched_barrier(0);
+        });
+
+        // finished bins of the end lane, one per row (two for |beta| = 2): lane j holds
+        // row P-1-j's (beta > 0, lanes 0..P-1) or lane 63-j does (beta < 0)
+        StaticFor<0, ND>::run([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int d = i;
+            if constexpr (d >= 2) {
+                constexpr int A = dir_alpha(d), B = dir_beta(d), AB = B < 0 ? -B : B;
+                constexpr int EO = chain_eoff<0, i>();
+                const int j = B > 0 ? lane : 63 - lane;
+                if (j < P) {
+                    // frame of the end lane, then the bin of row P-1-j
+                    const int32_t ue = B > 0 ? u0[i] - A * G * lane : u0[i] + A * G * (63 - lane);
+                    StaticFor<0, AB>::run([&](auto kc) {
+                        constexpr int k = decltype(kc)::value;
+                        const int32_t v = B > 0 ? B * (P - 1 - j) + k : AB * j + A * (G - 1) - AB + 1 + k;
+                        const uint32_t u = (uint32_t)(ue + v);
+                        atomicAdd(lds + doff[i] + (u + u / 8u), ebuf[EO + k]);
+                    });
+                }
+            }
+        });
+
+        if (seg_end) {
+            // every ring slot of every lane: bins v in [vlo, vlo + W) of its frame
+            StaticFor<0, ND>::run([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int d = i;
+                if constexpr (d >= 2) {
+                    constexpr int A = dir_alpha(d), B = dir_beta(d), AB = B < 0 ? -B : B;
+                    constexpr int W = chain_ring(d), RO = chain_off<0, i>();
+                    static_assert(chain_ok<d>(), "chained windows: inconsistent ring schedule");
+                    StaticFor<0, W>::run([&](auto kc) {
+                        constexpr int sl = decltype(kc)::value;
+                        constexpr int vb = chain_slot_bin<d>(sl);
+                        if constexpr (vb != CH_NONE) {
+                            const uint32_t u = (uint32_t)(u0[i] + vb);
+                            // a slot of a bin outside the image holds zero: skip it
+                            if (ring[RO + sl] != 0u) atomicAdd(lds + doff[i] + (u + u / 8u), ring[RO + sl]);
+                        }
+                    });
+#pragma unroll
+                    for (int k = 0; k < W; ++k) ring[RO + k] = 0u;
+                }
+            });
+            if constexpr (Tr0<ND>::has_xy) {
+                const uint32_t x0u = (uint32_t)x0;
+                uint32_t *base = lds + doff[0] + (x0u + x0u / 8u);
+                StaticFor<0, G>::run([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    atomicAdd(base + j, xy[j]);
+                });
+#pragma unroll
+                for (int j = 0; j < G; ++j) xy[j] = 0u;
+            }
+        }
+        ct = ct2;
+        per = per2;
+        cb = nb;
+    };
+
+    for (int32_t u = u_begin; u + 1 < u_end; ++u) unit(std::true_type{});
+    unit(std::false_type{});
+    (void)Z;
+}
+
 // One row side (segment) with everything needed to read its values, in registers (the
 // geometry itself lives in LDS).
 struct SegView {
@@ -351,14 +621,14 @@ __device__ __forceinline__ uint32_t seg_value(const SegView &v, int32_t a) {
 }
 
 // ------------------------------------------------------------ per-item driver
-template <typename VT, int D0, int ND, bool FAST>
+template <typename VT, int D0, int ND, bool FAST, bool CHAIN = false>
 __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int64_t pitch_y,
                            int64_t pitch_z, int64_t y, int64_t zs, int64_t ze, int R, int CT,
                            int32_t *__restrict__ rows_out, const int32_t *slot_off, const int32_t *slot_len,
                            int32_t *__restrict__ img, const int64_t *img_off, const int64_t *img_w,
                            uint32_t *lds, ItemGeom &ig) {
     using Tr = GroupTraits<D0, ND>;
-    constexpr int NW = slice_waves((int)sizeof(VT));
+    constexpr int NW = CHAIN ? CH_WAVES : slice_waves((int)sizeof(VT));
     const int tid = threadIdx.x;
 
     // geometry: one thread per direction, then the LDS offsets
@@ -385,14 +655,19 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
             }
             off += ig.dir[i].lds_len;
         }
-        ig.lds_dwords = off;
+        ig.lds_dwords = off + LDS_SINK;
         ig.n_chunks = (int32_t)((ze - zs + Tr::T - 1) / Tr::T);
     }
     __syncthreads();
     for (int i = tid; i < ig.lds_dwords; i += NW * 64) lds[i] = 0u;
     __syncthreads();
 
-    project_rows<VT, D0, ND, FAST>(vol + y * pitch_y, L, pitch_z, zs, ze, R, CT, lds, ig);
+    if constexpr (CHAIN) {
+        static_assert(FAST && D0 == 0, "chained windows: first group, exact rows only");
+        project_rows_chain<VT, ND>(vol + y * pitch_y, L, pitch_z, zs, ze, CT, lds, ig);
+    } else {
+        project_rows<VT, D0, ND, FAST>(vol + y * pitch_y, L, pitch_z, zs, ze, R, CT, lds, ig);
+    }
     __syncthreads();
 
     if (img) {
@@ -431,8 +706,8 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
 }
 
 // ------------------------------------------------------------ kernels
-template <typename VT, int D0, int ND, bool FAST>
-__global__ void __launch_bounds__(slice_waves((int)sizeof(VT)) * 64)
+template <typename VT, int D0, int ND, bool FAST, bool CHAIN = false>
+__global__ void __launch_bounds__((CHAIN ? CH_WAVES : slice_waves((int)sizeof(VT))) * 64)
 slice_kernel(SliceArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ ItemGeom ig;
@@ -440,7 +715,7 @@ slice_kernel(SliceArgs a) {
     const int64_t y = item / a.zsplits;
     const int64_t zs = (item % a.zsplits) * a.zrows;
     const int64_t ze = zs + a.zrows < a.N ? zs + a.zrows : a.N;
-    slice_item<VT, D0, ND, FAST>(reinterpret_cast<const VT *>(a.vol), a.L, a.N, a.pitch_y, a.pitch_z, y, zs,
+    slice_item<VT, D0, ND, FAST, CHAIN>(reinterpret_cast<const VT *>(a.vol), a.L, a.N, a.pitch_y, a.pitch_z, y, zs,
                                  ze, a.R, a.CT, a.rows + item * a.rl.row_stride, a.rl.slot_off,
                                  a.rl.slot_len, a.images, a.img_off, a.img_w, lds, ig);
 }
@@ -460,30 +735,31 @@ slice_batched_kernel(BatchSliceArgs a) {
 }
 
 // ------------------------------------------------------------ launch helpers
-template <typename VT, int D0, int ND, bool FAST>
+template <typename VT, int D0, int ND, bool FAST, bool CHAIN = false>
 hipError_t launch_one(const SliceArgs &a, int items, size_t lds, hipStream_t st) {
-    auto k = slice_kernel<VT, D0, ND, FAST>;
+    auto k = slice_kernel<VT, D0, ND, FAST, CHAIN>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, dim3(items), dim3(slice_waves((int)sizeof(VT)) * 64), lds, st, a);
+    const int nw = CHAIN ? CH_WAVES : slice_waves((int)sizeof(VT));
+    hipLaunchKernelGGL(k, dim3(items), dim3(nw * 64), lds, st, a);
     return hipGetLastError();
 }
 
-template <typename VT, int D0, bool FAST>
+template <typename VT, int D0, bool FAST, bool CHAIN = false>
 hipError_t launch_nd(int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st) {
     switch (nd) {
-        case 1: return launch_one<VT, D0, 1, FAST>(a, items, lds, st);
-        case 2: return launch_one<VT, D0, 2, FAST>(a, items, lds, st);
-        case 3: return launch_one<VT, D0, 3, FAST>(a, items, lds, st);
-        case 4: return launch_one<VT, D0, 4, FAST>(a, items, lds, st);
-        case 5: return launch_one<VT, D0, 5, FAST>(a, items, lds, st);
+        case 1: return launch_one<VT, D0, 1, FAST, CHAIN>(a, items, lds, st);
+        case 2: return launch_one<VT, D0, 2, FAST, CHAIN>(a, items, lds, st);
+        case 3: return launch_one<VT, D0, 3, FAST, CHAIN>(a, items, lds, st);
+        case 4: return launch_one<VT, D0, 4, FAST, CHAIN>(a, items, lds, st);
+        case 5: return launch_one<VT, D0, 5, FAST, CHAIN>(a, items, lds, st);
         default:
             if constexpr (D0 == 0) {
-                if (nd == 6) return launch_one<VT, D0, 6, FAST>(a, items, lds, st);
-                if (nd == 7) return launch_one<VT, D0, 7, FAST>(a, items, lds, st);
+                if (nd == 6) return launch_one<VT, D0, 6, FAST, CHAIN>(a, items, lds, st);
+                if (nd == 7) return launch_one<VT, D0, 7, FAST, CHAIN>(a, items, lds, st);
             }
             return hipErrorInvalidValue;
     }

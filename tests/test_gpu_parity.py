@@ -73,6 +73,8 @@ MOMENT_CASES = [
     ((32, 8, 128), np.uint16, 12),
     ((16, 8, 64), np.uint16, 0),
     ((16, 8, 64), np.uint8, 1),
+    ((32, 3, 512), np.uint16, 6),
+    ((96, 2, 1024), np.uint16, 5),
 ]
 
 
@@ -90,6 +92,12 @@ PATH_OVERRIDES = [
     ({"DPM_ZSPLITS": "3"}, (48, 10, 64), np.uint16, 7),     # z-split work items
     ({"DPM_ZSPLITS": "4", "DPM_NO_MFMA": "1"}, (70, 5, 64), np.uint8, 5),
     ({"DPM_FORCE_GENERIC": "1"}, (32, 8, 128), np.uint16, 6),
+    # chained-window projection (opt-in): rows of whole 64-lane tiles, 32-row units
+    ({"DPM_CHAIN": "1"}, (32, 3, 512), np.uint16, 6),
+    ({"DPM_CHAIN": "1"}, (96, 2, 1024), np.uint16, 5),
+    ({"DPM_CHAIN": "1"}, (64, 5, 512), np.uint16, 3),
+    ({"DPM_CHAIN": "1"}, (32, 4, 512), np.uint16, 1),
+    ({"DPM_CHAIN": "1"}, (64, 16, 512), np.uint16, 0),
 ]
 
 
@@ -131,11 +139,15 @@ def test_mri_phantom_256_order6(dpm):
     assert_moments_equal(res, onative.moments_hoisted(V, 6), 6, "mri256")
 
 
-def test_ct_512_order6_full(dpm):
+def test_ct_512_order6_full(dpm, monkeypatch):
     say("ct 512^3 K=6")
     V = synth.ct_phantom((512, 512, 512), seed=0)
+    ref = onative.moments_hoisted(V, 6)
     res = dpm.moments(to_dev(V), 6)
-    assert_moments_equal(res, onative.moments_hoisted(V, 6), 6, "ct512")
+    assert_moments_equal(res, ref, 6, "ct512")
+    monkeypatch.setenv("DPM_CHAIN", "1")
+    res = dpm.moments(to_dev(V), 6)
+    assert_moments_equal(res, ref, 6, "ct512 chained windows")
 
 
 def test_ct_128_order16_full(dpm):
