@@ -148,14 +148,13 @@ struct GroupTraits {
 };
 
 // ------------------------------------------------------------ step 1: projection
-template <typename VT, int D0, int ND, bool FAST>
+template <typename VT, int D0, int ND, bool FAST, int NW>
 __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pitch_z, int64_t zs,
                              int64_t ze, int R, int CT, uint32_t *lds, const ItemGeom &ig) {
     using Tr = GroupTraits<D0, ND>;
     using Vec = typename VecOf<VT>::type;
     constexpr int G = VecOf<VT>::G;
     constexpr int T = Tr::T;
-    constexpr int NW = slice_waves((int)sizeof(VT));
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int SR = 64 / R;
@@ -387,7 +386,7 @@ __device__ constexpr bool chain_ok() {
     return true;
 }
 
-template <typename VT, int ND>
+template <typename VT, int ND, int NW>
 __device__ void project_rows_chain(const VT *__restrict__ slice, int64_t L, int64_t pitch_z, int64_t zs,
                                    int64_t ze, int CT, uint32_t *lds, const ItemGeom &ig) {
     using Vec = typename VecOf<VT>::type;
@@ -395,7 +394,6 @@ __device__ void project_rows_chain(const VT *__restrict__ slice, int64_t L, int6
     static_assert(G == 8, "chained windows assume 8 voxels per lane");
     constexpr int P = CH_P, LA = CH_LA;
     constexpr int NRING = chain_off<0, ND>(), NE = chain_eoff<0, ND>();
-    constexpr int NW = CH_WAVES;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int32_t nper = (int32_t)((ze - zs) / P);  // caller guarantees (ze - zs) % P == 0
@@ -621,14 +619,13 @@ __device__ __forceinline__ uint32_t seg_value(const SegView &v, int32_t a) {
 }
 
 // ------------------------------------------------------------ per-item driver
-template <typename VT, int D0, int ND, bool FAST, bool CHAIN = false>
+template <typename VT, int D0, int ND, bool FAST, bool CHAIN, int NW>
 __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int64_t pitch_y,
                            int64_t pitch_z, int64_t y, int64_t zs, int64_t ze, int R, int CT,
                            int32_t *__restrict__ rows_out, const int32_t *slot_off, const int32_t *slot_len,
                            int32_t *__restrict__ img, const int64_t *img_off, const int64_t *img_w,
                            uint32_t *lds, ItemGeom &ig) {
     using Tr = GroupTraits<D0, ND>;
-    constexpr int NW = CHAIN ? CH_WAVES : slice_waves((int)sizeof(VT));
     const int tid = threadIdx.x;
 
     // geometry: one thread per direction, then the LDS offsets
@@ -664,9 +661,9 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
 
     if constexpr (CHAIN) {
         static_assert(FAST && D0 == 0, "chained windows: first group, exact rows only");
-        project_rows_chain<VT, ND>(vol + y * pitch_y, L, pitch_z, zs, ze, CT, lds, ig);
+        project_rows_chain<VT, ND, NW>(vol + y * pitch_y, L, pitch_z, zs, ze, CT, lds, ig);
     } else {
-        project_rows<VT, D0, ND, FAST>(vol + y * pitch_y, L, pitch_z, zs, ze, R, CT, lds, ig);
+        project_rows<VT, D0, ND, FAST, NW>(vol + y * pitch_y, L, pitch_z, zs, ze, R, CT, lds, ig);
     }
     __syncthreads();
 
@@ -715,20 +712,24 @@ slice_kernel(SliceArgs a) {
     const int64_t y = item / a.zsplits;
     const int64_t zs = (item % a.zsplits) * a.zrows;
     const int64_t ze = zs + a.zrows < a.N ? zs + a.zrows : a.N;
-    slice_item<VT, D0, ND, FAST, CHAIN>(reinterpret_cast<const VT *>(a.vol), a.L, a.N, a.pitch_y, a.pitch_z, y, zs,
+    slice_item<VT, D0, ND, FAST, CHAIN, CHAIN ? CH_WAVES : slice_waves((int)sizeof(VT))>(reinterpret_cast<const VT *>(a.vol), a.L, a.N, a.pitch_y, a.pitch_z, y, zs,
                                  ze, a.R, a.CT, a.rows + item * a.rl.row_stride, a.rl.slot_off,
                                  a.rl.slot_len, a.images, a.img_off, a.img_w, lds, ig);
 }
 
+// Batched items are small slices of small volumes: one wave per item, so that many
+// items run side by side on a CU.
+constexpr int BATCH_WAVES = 1;
+
 template <typename VT, int D0, int ND>
-__global__ void __launch_bounds__(slice_waves((int)sizeof(VT)) * 64)
+__global__ void __launch_bounds__(BATCH_WAVES * 64)
 slice_batched_kernel(BatchSliceArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ ItemGeom ig;
     const BatchItem it = a.items[blockIdx.x];
     const RoiDesc &rd = a.rois[it.roi];
     if (rd.elem != (int)sizeof(VT)) return;
-    slice_item<VT, D0, ND, false>(reinterpret_cast<const VT *>(a.packed + rd.offset), rd.L, rd.N, rd.L,
+    slice_item<VT, D0, ND, false, false, BATCH_WAVES>(reinterpret_cast<const VT *>(a.packed + rd.offset), rd.L, rd.N, rd.L,
                                   rd.L * rd.M, it.y, it.zs, it.ze, rd.R, rd.CT,
                                   a.rows + rd.row_base + (int64_t)it.y * rd.row_stride, rd.slot_off,
                                   rd.slot_len, nullptr, nullptr, nullptr, lds, ig);
@@ -773,7 +774,7 @@ hipError_t launch_b_one(const BatchSliceArgs &a, int items, size_t lds, hipStrea
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, dim3(items), dim3(slice_waves((int)sizeof(VT)) * 64), lds, st, a);
+    hipLaunchKernelGGL(k, dim3(items), dim3(BATCH_WAVES * 64), lds, st, a);
     return hipGetLastError();
 }
 
