@@ -45,7 +45,7 @@ struct BPlan {
     int amax = 64;
     std::vector<RoiDesc> rd;
     std::vector<BatchItem> it;
-    size_t off_rd = 0, off_it = 0, off_rows = 0, off_part = 0, total = 0;
+    size_t off_rd = 0, off_it = 0, off_rows = 0, off_part = 0, off_tmap = 0, total = 0;
 };
 
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
@@ -146,7 +146,8 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
         d.nitems = (int32_t)d.M;
         item0 += (int32_t)d.M;
         d.tile0 = tile0;
-        tile0 += nsl * (int)((d.M + 15) / 16);
+        d.ntiles = nsl * (int)((d.M + 15) / 16);
+        tile0 += d.ntiles;
         order.push_back({d.L * d.N, i});
     }
     p.ntiles = tile0;
@@ -165,10 +166,7 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
         for (int64_t y = 0; y < p.rd[i].M; ++y) {
             BatchItem b{};
             b.roi = i;
-            b.slot = (int32_t)p.it.size();
             b.y = (int32_t)y;
-            b.zs = 0;
-            b.ze = (int32_t)p.rd[i].N;
             p.it.push_back(b);
         }
     }
@@ -177,7 +175,8 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     p.off_it = al(sizeof(RoiDesc) * n);
     p.off_rows = p.off_it + al(sizeof(BatchItem) * p.it.size());
     p.off_part = p.off_rows + al((size_t)row_base * 4);
-    p.total = p.off_part + al((size_t)p.ntiles * (K + 1) * (K + 1) * p.nlr * 4);
+    p.off_tmap = p.off_part + al((size_t)p.ntiles * (K + 1) * (K + 1) * p.nlr * 4);
+    p.total = p.off_tmap + al((size_t)p.ntiles * 4);
     return DPM_OK;
 }
 
@@ -220,6 +219,7 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
     BatchItem *dit = reinterpret_cast<BatchItem *>(ws + p.off_it);
     int32_t *rows = reinterpret_cast<int32_t *>(ws + p.off_rows);
     uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
+    int32_t *tmap = reinterpret_cast<int32_t *>(ws + p.off_tmap);
     PowTab pt{};
     if (p.mfma && (rc = batched_powtab(p.amax, max_order, pt))) return rc;
     hipError_t e = hipSuccess;
@@ -243,7 +243,7 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
     }
     const int nd = max_order + 1;
     batched_prof_mark(0, st);
-    BatchSliceArgs a{static_cast<const uint8_t *>(packed), drd, dit, max_order, rows};
+    BatchSliceArgs a{static_cast<const uint8_t *>(packed), drd, dit, max_order, rows, tmap};
     if (p.has_u16) e = launch_slice_batched(2, 0, nd, a, p.items, p.lds, st);
     if (e == hipSuccess && p.has_u8) e = launch_slice_batched(1, 0, nd, a, p.items, p.lds, st);
     if (e == hipSuccess) batched_prof_mark(1, st);
@@ -251,11 +251,13 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
         PowerArgs pa{};
         pa.rows = rows;
         pa.rois = drd;
+        pa.tile_roi = tmap;
         pa.nrois = n_rois;
         pa.nitems = p.items;
         pa.zsplits = 1;
         pa.K = max_order;
         pa.ntiles = p.ntiles;
+        pa.max_len = p.amax;
         pa.pow = pt;
         pa.part = part;
         e = launch_power(p.nls, p.nlr, pa, st);

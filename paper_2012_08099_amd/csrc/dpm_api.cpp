@@ -430,6 +430,7 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
     pa.zsplits = p.zsplits;
     pa.K = p.K;
     pa.ntiles = p.ntiles;
+    for (int s = 0; s < NSLOT; ++s) pa.max_len = std::max(pa.max_len, p.rl.slot_len[s]);
     pa.pow = pt;
     pa.part = part;
     prof_mark(1, st);

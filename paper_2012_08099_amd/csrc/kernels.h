@@ -55,16 +55,16 @@ struct RoiDesc {
     int32_t item0;             // first work item (= first row block) of this ROI
     int32_t nitems;
     int32_t tile0;             // first power-sum tile of this ROI
+    int32_t ntiles;            // power-sum tiles of this ROI
     int64_t row_base;          // int32 offset of item0's rows
     int32_t row_stride;        // int32 values per item
     int32_t slot_off[14];      // orders <= 6: slots 0..13
     int32_t slot_len[14];
 };
 
-struct BatchItem {
+struct BatchItem {              // one y-slice of one ROI, whole z range
     int32_t roi;
-    int32_t slot;              // row of the partial-sum table
-    int32_t y, zs, ze;
+    int32_t y;
 };
 
 struct BatchSliceArgs {
@@ -73,6 +73,7 @@ struct BatchSliceArgs {
     const BatchItem *items;
     int32_t K;
     int32_t *rows;
+    int32_t *tile_roi;         // written here: ROI of every power-sum tile
 };
 
 // Power sums of the image rows, weighted in y per tile of 16 items:
@@ -82,11 +83,13 @@ struct PowerArgs {
     const int32_t *rows;
     RowLayout rl;               // single volume
     const RoiDesc *rois;        // batched (null for a single volume)
+    const int32_t *tile_roi;    // batched: ROI of every tile
     int32_t nrois;
     int32_t nitems;
     int32_t zsplits;            // single volume: y of item i is i / zsplits
     int32_t K;
     int32_t ntiles;             // work tiles (16 items x one slot)
+    int32_t max_len;            // longest row slot (values)
     PowTab pow;                 // null b: VALU path
     uint32_t *part;
 };

@@ -54,13 +54,7 @@ __device__ bool decode_tile(const PowerArgs &a, int tile, TileInfo &ti) {
         }
         return false;
     }
-    int lo = 0, hi = a.nrois - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (a.rois[mid].tile0 <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    const RoiDesc &rd = a.rois[lo];
+    const RoiDesc &rd = a.rois[a.tile_roi[tile]];
     const int ipt = (int)((rd.M + 15) / 16);
     int local = tile - rd.tile0, cnt = 0;
     for (int s = 0; s < 14 && s <= 2 * a.K + 1; ++s) {
@@ -133,18 +127,23 @@ __device__ __forceinline__ void yweight_store(const PowerArgs &a, const TileInfo
     }
 }
 
-// One workgroup per tile (16 items x one slot).  The waves split the K-steps of 64
-// coordinates (wave w takes steps w, w + W, ...), loading PW_PF steps at once; their
+// One workgroup per tile (16 items x one slot).  The MW waves split the K-steps of 64
+// coordinates (wave w takes steps w, w + MW, ...), loading PW_PF steps at once; their
 // int32 limb-pair sums meet in LDS; then every thread reassembles one (item, k) sum.
-constexpr int PW_MW = 4;   // waves of the matrix-core kernel
+// Long rows take four waves; short rows (a few K-steps, as in batches of small volumes)
+// take one, which then needs no LDS clearing or atomics and reassembles one 16-column
+// tile at a time.
+constexpr int PW_MW = 4;   // waves of the matrix-core kernel for long rows
 constexpr int PW_PF = 3;   // K-steps per wave whose loads are in flight together
 constexpr int PW_NTP = 4;  // 16-column tiles per pass (4 P-limbs x 4 tiles x 4 = 64 VGPRs)
+constexpr int PW_SHORT = 512;  // rows up to this many values take the one-wave kernel
 
-template <int NLS, int NLR>
-__global__ void __launch_bounds__(PW_MW * 64) power_mfma_kernel(PowerArgs a) {
+template <int NLS, int NLR, int MW>
+__global__ void __launch_bounds__(MW * 64) power_mfma_kernel(PowerArgs a) {
     typedef int v4i __attribute__((ext_vector_type(4)));
-    constexpr int T = PW_MW * 64;
-    __shared__ int32_t ctab[4][PW_NTP][256];
+    constexpr int T = MW * 64;
+    constexpr int NCT = MW == 1 ? 1 : PW_NTP;  // column tiles held in LDS at once
+    __shared__ int32_t ctab[4][NCT][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     TileInfo ti;
     if (!decode_tile(a, blockIdx.x, ti)) return;  // uniform over the workgroup
@@ -164,19 +163,44 @@ __global__ void __launch_bounds__(PW_MW * 64) power_mfma_kernel(PowerArgs a) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) mw::set_zero(R[j]);
 
+    // R_k(item) += sum_u 2^(7u) sum_c 2^(7c) C_c[item][col(k, u)] over the columns of
+    // tiles [tb, tb + n), whose limb-pair sums sit in ctab[c][tile - tb]
+    auto reassemble = [&](int tb, int n) {
+        const int colp0 = tb * 16, colp1 = (tb + n) * 16;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int k = d + (tid >> 4) + (T / 16) * j;
+            if (k > K) break;
+            const int cs0 = a.pow.colstart[k], cs1 = a.pow.colstart[k + 1];
+            const int lo = cs0 > colp0 ? cs0 : colp0, hi = cs1 < colp1 ? cs1 : colp1;
+            for (int col = lo; col < hi; ++col) {
+                const int tp = (col >> 4) - tb, cc = col & 15;
+                uint64_t vsum = 0;  // < 2^27 * 2^22: exact
+#pragma unroll
+                for (int c = 0; c < 4; ++c) vsum += (uint64_t)(uint32_t)ctab[c][tp][ei * 16 + cc] << (7 * c);
+                if (!vsum) continue;
+                const int sh = 7 * (col - cs0);
+                add_shifted(R[j], (uint32_t)vsum, sh);
+                add_shifted(R[j], (uint32_t)(vsum >> 32), sh + 32);
+            }
+        }
+    };
+
     for (int t0 = 0; t0 < nt; t0 += PW_NTP) {
-        for (int i = tid; i < 4 * PW_NTP * 256; i += T) (&ctab[0][0][0])[i] = 0;
-        __syncthreads();
+        if (MW > 1) {
+            for (int i = tid; i < 4 * NCT * 256; i += T) (&ctab[0][0][0])[i] = 0;
+            __syncthreads();
+        }
         v4i acc[4][PW_NTP];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int tp = 0; tp < PW_NTP; ++tp) acc[c][tp] = v4i{0, 0, 0, 0};
-        for (int ks0 = wave; ks0 < nks; ks0 += PW_PF * PW_MW) {
+        for (int ks0 = wave; ks0 < nks; ks0 += PW_PF * MW) {
             uint4 rq[PW_PF][4], bq[PW_PF][PW_NTP];
 #pragma unroll
             for (int f = 0; f < PW_PF; ++f) {
-                const int ks = ks0 + f * PW_MW;
+                const int ks = ks0 + f * MW;
                 const bool ok = ks < nks;
                 const uint4 *p = reinterpret_cast<const uint4 *>(rp + ks * 64);
 #pragma unroll
@@ -187,7 +211,7 @@ __global__ void __launch_bounds__(PW_MW * 64) power_mfma_kernel(PowerArgs a) {
             }
 #pragma unroll
             for (int f = 0; f < PW_PF; ++f) {
-                if (ks0 + f * PW_MW >= nks) break;
+                if (ks0 + f * MW >= nks) break;
                 const uint32_t v[16] = {rq[f][0].x, rq[f][0].y, rq[f][0].z, rq[f][0].w,
                                         rq[f][1].x, rq[f][1].y, rq[f][1].z, rq[f][1].w,
                                         rq[f][2].x, rq[f][2].y, rq[f][2].z, rq[f][2].w,
@@ -214,35 +238,32 @@ __global__ void __launch_bounds__(PW_MW * 64) power_mfma_kernel(PowerArgs a) {
                 }
             }
         }
-        // partial limb-pair sums of the waves -> ctab[c][tile][item][col]
+        if (MW > 1) {
+            // partial limb-pair sums of the waves -> ctab[c][tile][item][col]
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+            for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int tp = 0; tp < PW_NTP; ++tp)
+                for (int tp = 0; tp < PW_NTP; ++tp)
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (acc[c][tp][e]) atomicAdd(&ctab[c][tp][((lane >> 4) * 4 + e) * 16 + (lane & 15)], acc[c][tp][e]);
-        __syncthreads();
-        // R_k(item) += sum_u 2^(7u) sum_c 2^(7c) C_c[item][col(k, u)]
-        const int colp0 = t0 * 16, colp1 = (t0 + PW_NTP) * 16;
+                    for (int e = 0; e < 4; ++e)
+                        if (acc[c][tp][e]) atomicAdd(&ctab[c][tp][((lane >> 4) * 4 + e) * 16 + (lane & 15)], acc[c][tp][e]);
+            __syncthreads();
+            reassemble(t0, PW_NTP);
+            __syncthreads();
+        } else {
+            // one wave holds the whole sums: one column tile at a time through LDS
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int k = d + (tid >> 4) + (T / 16) * j;
-            if (k > K) break;
-            const int cs0 = a.pow.colstart[k], cs1 = a.pow.colstart[k + 1];
-            const int lo = cs0 > colp0 ? cs0 : colp0, hi = cs1 < colp1 ? cs1 : colp1;
-            for (int col = lo; col < hi; ++col) {
-                const int tp = (col >> 4) - t0, cc = col & 15;
-                uint64_t vsum = 0;  // < 2^27 * 2^22: exact
+            for (int tp = 0; tp < PW_NTP; ++tp) {
+                if (t0 + tp >= nt) break;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) vsum += (uint64_t)(uint32_t)ctab[c][tp][ei * 16 + cc] << (7 * c);
-                if (!vsum) continue;
-                const int sh = 7 * (col - cs0);
-                add_shifted(R[j], (uint32_t)vsum, sh);
-                add_shifted(R[j], (uint32_t)(vsum >> 32), sh + 32);
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ctab[c][0][((lane >> 4) * 4 + e) * 16 + (lane & 15)] = acc[c][tp][e];
+                __syncthreads();
+                reassemble(t0 + tp, 1);
+                __syncthreads();
             }
         }
-        __syncthreads();
     }
     yweight_store<T, NLS, NLR, NJ>(a, ti, blockIdx.x, d, R);
 }
@@ -308,7 +329,10 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_valu_kernel(PowerArgs a) 
 template <int NLS, int NLR>
 static hipError_t power_go(const PowerArgs &a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
-    if (a.pow.b) hipLaunchKernelGGL((power_mfma_kernel<NLS, NLR>), dim3(a.ntiles), dim3(PW_MW * 64), 0, st, a);
+    if (a.pow.b && a.max_len <= PW_SHORT)
+        hipLaunchKernelGGL((power_mfma_kernel<NLS, NLR, 1>), dim3(a.ntiles), dim3(64), 0, st, a);
+    else if (a.pow.b)
+        hipLaunchKernelGGL((power_mfma_kernel<NLS, NLR, PW_MW>), dim3(a.ntiles), dim3(PW_MW * 64), 0, st, a);
     else hipLaunchKernelGGL((power_valu_kernel<NLS, NLR>), dim3(a.ntiles), dim3(PW_WAVES * 64), 0, st, a);
     return hipGetLastError();
 }

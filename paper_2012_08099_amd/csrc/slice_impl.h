@@ -729,8 +729,11 @@ slice_batched_kernel(BatchSliceArgs a) {
     const BatchItem it = a.items[blockIdx.x];
     const RoiDesc &rd = a.rois[it.roi];
     if (rd.elem != (int)sizeof(VT)) return;
+    // the ROI's M items together label its power-sum tiles
+    for (int64_t j = it.y + rd.M * (int64_t)threadIdx.x; j < rd.ntiles; j += rd.M * BATCH_WAVES * 64)
+        a.tile_roi[rd.tile0 + j] = it.roi;
     slice_item<VT, D0, ND, false, false, BATCH_WAVES>(reinterpret_cast<const VT *>(a.packed + rd.offset), rd.L, rd.N, rd.L,
-                                  rd.L * rd.M, it.y, it.zs, it.ze, rd.R, rd.CT,
+                                  rd.L * rd.M, it.y, 0, rd.N, rd.R, rd.CT,
                                   a.rows + rd.row_base + (int64_t)it.y * rd.row_stride, rd.slot_off,
                                   rd.slot_len, nullptr, nullptr, nullptr, lds, ig);
 }
