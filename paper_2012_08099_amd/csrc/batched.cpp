@@ -1,6 +1,7 @@
 // Batched regions of interest: many independent volumes of uneven size in one
 // launch sequence (projection kernel over every (ROI, y-slice) work item, power-sum
-// tiles of every ROI in one grid, one recombination workgroup per (ROI, moment)).  Work items are laid out
+// tiles of every ROI in one grid, one recombination workgroup per (ROI, moment)).  A prep kernel
+// writes each ROI's geometry, its work items and its tile labels on the device; items are laid out
 // longest-first (LPT order) so the large ROIs start early and the small ones fill the
 // tail of the grid.
 #include <hip/hip_runtime.h>
@@ -44,8 +45,7 @@ struct BPlan {
     bool mfma = false;
     int amax = 64;
     std::vector<RoiDesc> rd;
-    std::vector<BatchItem> it;
-    size_t off_rd = 0, off_it = 0, off_rows = 0, off_part = 0, off_tmap = 0, total = 0;
+    size_t off_rd = 0, off_it = 0, off_geom = 0, off_rows = 0, off_part = 0, off_tmap = 0, total = 0;
 };
 
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
@@ -142,7 +142,6 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
         d.row_stride = off;
         d.row_base = row_base;
         row_base += (int64_t)off * d.M;
-        d.item0 = item0;
         d.nitems = (int32_t)d.M;
         item0 += (int32_t)d.M;
         d.tile0 = tile0;
@@ -161,19 +160,16 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     p.mfma = small_p && p.amax <= 8192 && batched_pow_columns(p.amax, K, cs);
     // projection work items, largest slices first (LPT order)
     std::stable_sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
+    int32_t pos = 0;
     for (auto &o : order) {
-        const int i = o.second;
-        for (int64_t y = 0; y < p.rd[i].M; ++y) {
-            BatchItem b{};
-            b.roi = i;
-            b.y = (int32_t)y;
-            p.it.push_back(b);
-        }
+        p.rd[o.second].item_pos = pos;
+        pos += (int32_t)p.rd[o.second].M;
     }
-    p.items = (int)p.it.size();
+    p.items = item0;
     p.off_rd = 0;
     p.off_it = al(sizeof(RoiDesc) * n);
-    p.off_rows = p.off_it + al(sizeof(BatchItem) * p.it.size());
+    p.off_geom = p.off_it + al(sizeof(BatchItem) * (size_t)p.items);
+    p.off_rows = p.off_geom + al(sizeof(ItemGeom) * (size_t)n);
     p.off_part = p.off_rows + al((size_t)row_base * 4);
     p.off_tmap = p.off_part + al((size_t)p.ntiles * (K + 1) * (K + 1) * p.nlr * 4);
     p.total = p.off_tmap + al((size_t)p.ntiles * 4);
@@ -227,14 +223,11 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
         int dev = 0;
         e = hipGetDevice(&dev);
         std::lock_guard<std::mutex> lk(g_stage_mu);
-        const size_t brd = sizeof(RoiDesc) * p.rd.size(), bit = sizeof(BatchItem) * p.it.size();
-        Staging *sg = e == hipSuccess ? stage_acquire(brd + bit, dev) : nullptr;
+        const size_t brd = sizeof(RoiDesc) * p.rd.size();
+        Staging *sg = e == hipSuccess ? stage_acquire(brd, dev) : nullptr;
         if (!sg) return e == hipSuccess ? DPM_ENOMEM : (batched_set_error((int)e), DPM_EDEVICE);
         std::memcpy(sg->p, p.rd.data(), brd);
-        std::memcpy(static_cast<uint8_t *>(sg->p) + brd, p.it.data(), bit);
         e = hipMemcpyAsync(drd, sg->p, brd, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(dit, static_cast<uint8_t *>(sg->p) + brd, bit, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipEventRecord(sg->ev, st);
     }
     if (e != hipSuccess) {
@@ -243,8 +236,10 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
     }
     const int nd = max_order + 1;
     batched_prof_mark(0, st);
-    BatchSliceArgs a{static_cast<const uint8_t *>(packed), drd, dit, max_order, rows, tmap};
-    if (p.has_u16) e = launch_slice_batched(2, 0, nd, a, p.items, p.lds, st);
+    BatchSliceArgs a{static_cast<const uint8_t *>(packed), drd, dit, max_order, rows, tmap,
+                     reinterpret_cast<ItemGeom *>(ws + p.off_geom)};
+    e = launch_batched_prep(nd, a, n_rois, st);
+    if (e == hipSuccess && p.has_u16) e = launch_slice_batched(2, 0, nd, a, p.items, p.lds, st);
     if (e == hipSuccess && p.has_u8) e = launch_slice_batched(1, 0, nd, a, p.items, p.lds, st);
     if (e == hipSuccess) batched_prof_mark(1, st);
     if (e == hipSuccess) {

@@ -52,7 +52,7 @@ struct RoiDesc {
     int64_t L, M, N;
     int32_t elem;              // bytes per voxel
     int32_t R, CT;
-    int32_t item0;             // first work item (= first row block) of this ROI
+    int32_t item_pos;          // launch position of this ROI's first work item
     int32_t nitems;
     int32_t tile0;             // first power-sum tile of this ROI
     int32_t ntiles;            // power-sum tiles of this ROI
@@ -70,10 +70,11 @@ struct BatchItem {              // one y-slice of one ROI, whole z range
 struct BatchSliceArgs {
     const uint8_t *packed;
     const RoiDesc *rois;
-    const BatchItem *items;
+    BatchItem *items;          // written by the prep kernel, read by the projection
     int32_t K;
     int32_t *rows;
-    int32_t *tile_roi;         // written here: ROI of every power-sum tile
+    int32_t *tile_roi;         // written by the prep kernel: ROI of every power-sum tile
+    ItemGeom *geom;            // written by the prep kernel: geometry of every ROI
 };
 
 // Power sums of the image rows, weighted in y per tile of 16 items:
@@ -99,6 +100,9 @@ hipError_t launch_power(int nls, int nlr, const PowerArgs &a, hipStream_t st);
 // that are whole 32-row units)
 hipError_t launch_slice(int elem, bool fast, bool chain, int g, int nd, const SliceArgs &a, int items, size_t lds,
                         hipStream_t st);
+// One workgroup per ROI: its geometry, its work items (launch order item_pos + y) and
+// the labels of its power-sum tiles.
+hipError_t launch_batched_prep(int nd, const BatchSliceArgs &a, int nrois, hipStream_t st);
 hipError_t launch_slice_batched(int elem, int g, int nd, const BatchSliceArgs &a, int items, size_t lds,
                                 hipStream_t st);
 

@@ -119,16 +119,31 @@ __device__ __forceinline__ typename VecOf<VT>::type load_lane(const VT *row, int
         // streamed once: non-temporal, so it does not evict the small shared tables
         const Raw r = __builtin_nontemporal_load(reinterpret_cast<const Raw *>(row + x0));
         __builtin_memcpy(&v, &r, sizeof(Vec));
-    } else {
-        if (in) {
-            uint32_t w[sizeof(Vec) / 4] = {};
+    } else if (in) {
+        // Any alignment, ragged row end: the aligned dwords that hold at least one
+        // byte of the lane's nv voxels (never a dword past the row's last byte, so never
+        // a page the row does not touch), funnel-shifted into place; bytes past the row
+        // end are cleared.
+        constexpr int NB = (int)sizeof(Vec);  // bytes of a full lane
+        constexpr int NDW = NB / 4 + 1;
+        const int64_t nv = L - x0 < G ? L - x0 : G;  // >= 1 (x0 < L)
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(row + x0);
+        const uintptr_t last = a0 + (uintptr_t)nv * sizeof(VT) - 1;
+        const uint32_t *dw = reinterpret_cast<const uint32_t *>(a0 & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(a0 & 3);
+        uint32_t d[NDW];
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                uint32_t e = (x0 + j < L) ? (uint32_t)row[x0 + j] : 0u;
-                w[(j * sizeof(VT)) / 4] |= e << (8 * ((j * sizeof(VT)) & 3));
-            }
-            __builtin_memcpy(&v, w, sizeof(Vec));
+        for (int k = 0; k < NDW; ++k)
+            d[k] = (reinterpret_cast<uintptr_t>(dw + k) <= last) ? dw[k] : 0u;
+        const int nbv = (int)(nv * (int64_t)sizeof(VT));
+        uint32_t w[NB / 4];
+#pragma unroll
+        for (int i = 0; i < NB / 4; ++i) {
+            const uint32_t x = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+            const int keep = nbv - 4 * i;  // bytes of this dword inside the row
+            w[i] = keep >= 4 ? x : keep <= 0 ? 0u : (x & ((1u << (8 * keep)) - 1u));
         }
+        __builtin_memcpy(&v, w, sizeof(Vec));
     }
     return v;
 }
@@ -624,12 +639,17 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
                            int64_t pitch_z, int64_t y, int64_t zs, int64_t ze, int R, int CT,
                            int32_t *__restrict__ rows_out, const int32_t *slot_off, const int32_t *slot_len,
                            int32_t *__restrict__ img, const int64_t *img_off, const int64_t *img_w,
-                           uint32_t *lds, ItemGeom &ig) {
+                           uint32_t *lds, ItemGeom &ig, const ItemGeom *pre = nullptr) {
     using Tr = GroupTraits<D0, ND>;
     const int tid = threadIdx.x;
 
-    // geometry: one thread per direction, then the LDS offsets
-    if (tid < ND) {
+    if (pre) {
+        // precomputed for the whole z range (batched items)
+        const int32_t *src = reinterpret_cast<const int32_t *>(pre);
+        int32_t *dst = reinterpret_cast<int32_t *>(&ig);
+        for (int i = tid; i < (int)(sizeof(ItemGeom) / 4); i += NW * 64) dst[i] = src[i];
+    } else if (tid < ND) {
+        // geometry: one thread per direction, then the LDS offsets
         DirGeom dg;
         int32_t an, hn, ap, hp;
         dir_geometry(Tr::g, tid, VecOf<VT>::G, L, N, zs, ze, dg, an, hn, ap, hp);
@@ -640,7 +660,7 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
         ig.seg_ahi[2 * tid + 1] = hp;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (!pre && tid == 0) {
         int32_t off = 0;
         ig.yz_off = -1;
         ig.yz_stride = 0;
@@ -729,13 +749,10 @@ slice_batched_kernel(BatchSliceArgs a) {
     const BatchItem it = a.items[blockIdx.x];
     const RoiDesc &rd = a.rois[it.roi];
     if (rd.elem != (int)sizeof(VT)) return;
-    // the ROI's M items together label its power-sum tiles
-    for (int64_t j = it.y + rd.M * (int64_t)threadIdx.x; j < rd.ntiles; j += rd.M * BATCH_WAVES * 64)
-        a.tile_roi[rd.tile0 + j] = it.roi;
     slice_item<VT, D0, ND, false, false, BATCH_WAVES>(reinterpret_cast<const VT *>(a.packed + rd.offset), rd.L, rd.N, rd.L,
                                   rd.L * rd.M, it.y, 0, rd.N, rd.R, rd.CT,
                                   a.rows + rd.row_base + (int64_t)it.y * rd.row_stride, rd.slot_off,
-                                  rd.slot_len, nullptr, nullptr, nullptr, lds, ig);
+                                  rd.slot_len, nullptr, nullptr, nullptr, lds, ig, a.geom + it.roi);
 }
 
 // ------------------------------------------------------------ launch helpers

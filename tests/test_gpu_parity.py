@@ -112,6 +112,24 @@ def test_moments_forced_paths(dpm, monkeypatch, env, shape, dt, K):
     assert_moments_equal(res, oracle.moments_exact(V, K), K, f"{env} {shape} K={K}")
 
 
+@pytest.mark.parametrize("dt", [np.uint8, np.uint16])
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_unaligned_volume_at_buffer_end(dpm, dt, shift):
+    """A volume whose first voxel is not 4-byte aligned and whose last voxel is the last
+    element of its buffer: the generic lane loads read only aligned dwords that hold
+    voxels of the row and shift them into place."""
+    import torch
+    say("unaligned", dt.__name__, shift)
+    V = synth.uniform_volume((11, 5, 37), dt, seed=shift)
+    src = to_dev(V).reshape(-1)
+    flat = torch.empty(shift + src.numel(), dtype=src.dtype, device=src.device)
+    flat[shift:] = src
+    vol = flat[shift:].view(V.shape)
+    assert vol.data_ptr() % 4 != 0 or dt is np.uint16
+    res = dpm.moments(vol, 6)
+    assert_moments_equal(res, oracle.moments_exact(V, 6), 6, f"unaligned {dt.__name__} +{shift}")
+
+
 def test_all_zero_volume(dpm):
     V = np.zeros((48, 16, 64), dtype=np.uint16)
     res = dpm.moments(to_dev(V), 6)
