@@ -354,7 +354,23 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
         }
         p.amax = (int)amax;
     }
-    p.ntiles = p.nslots_used * ((p.items + 15) / 16);
+    {
+        // power-sum tiles; on the matrix cores each covers at most kchunk steps of 64
+        // values of a, so long rows spread over more workgroups
+        int kc = p.mfma ? 8 : (1 << 30);
+        if (const char *e = std::getenv("DPM_PW_KCHUNK")) {
+            if (atoi(e) > 0 && p.mfma) kc = atoi(e);
+        }
+        const int32_t ipt = (int32_t)((p.items + 15) / 16);
+        p.rl.kchunk = kc;
+        p.rl.tile0[0] = 0;
+        for (int sl = 0; sl < NSLOT; ++sl) {
+            const int32_t nks = p.rl.slot_len[sl] / 64;
+            p.rl.nck[sl] = nks ? (nks + kc - 1) / kc : 0;
+            p.rl.tile0[sl + 1] = p.rl.tile0[sl] + ipt * p.rl.nck[sl];
+        }
+        p.ntiles = p.rl.tile0[NSLOT];
+    }
     p.part_bytes = align_up((size_t)p.ntiles * (K + 1) * (K + 1) * p.nlr * 4);
     p.ws_bytes = p.rows_bytes + p.part_bytes;
     return DPM_OK;
@@ -442,8 +458,7 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
     f.rois = nullptr;
     f.nvol = 1;
     f.K = p.K;
-    f.slot_mask = p.slot_mask;
-    f.ipt = (p.items + 15) / 16;
+    for (int s = 0; s <= NSLOT; ++s) f.tile0[s] = p.rl.tile0[s];
     f.exact = exact;
     f.fp64 = fp64;
     e = launch_finish(p.nlr, f, st);

@@ -32,6 +32,11 @@ struct RowLayout {
     int32_t slot_off[NSLOT];
     int32_t slot_len[NSLOT];   // multiple of 64; 0 = empty slot
     int64_t row_stride;        // int32 values per item
+    // power-sum tiles: 16 items x one slot x at most kchunk steps of 64 values of a;
+    // slot s owns tiles [tile0[s], tile0[s+1]), nck[s] chunks per block of 16 items
+    int32_t tile0[NSLOT + 1];
+    int32_t nck[NSLOT];
+    int32_t kchunk;
 };
 
 struct SliceArgs {
@@ -111,8 +116,7 @@ struct FinishArgs {
     const uint32_t *part;      // tile partials (PowerArgs::part)
     const RoiDesc *rois;       // batched (null for a single volume)
     int32_t nvol, K;
-    uint64_t slot_mask;        // single volume: bit s = slot s holds data
-    int32_t ipt;               // single volume: tiles per slot
+    int32_t tile0[NSLOT + 1];  // single volume: tiles of slot s are [tile0[s], tile0[s+1])
     void *exact;               // dpm_i128 [vol][n_moments(min(K,4))] or null
     double *fp64;              // [vol][n_moments(K)] or null
 };

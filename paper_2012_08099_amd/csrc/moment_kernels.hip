@@ -37,46 +37,58 @@ __device__ __forceinline__ void decode_moment(int m, int &p, int &q, int &r) {
     r = n - p - q;
 }
 
-constexpr int FIN_THREADS = 256;
+constexpr int FIN_THREADS = 256;   // one volume: up to 2 * 16 * (K+1) tiles per moment
+constexpr int FIN_THREADS_ROI = 64; // batched ROIs: a few tiles per moment, one wave
 constexpr int FIN_BATCH = 4;  // entries whose loads are in flight together
 
-template <int NLR>
-__global__ void __launch_bounds__(FIN_THREADS) finish_kernel(FinishArgs a) {
-    __shared__ uint32_t wsum[FIN_THREADS / 64][NLR];
-    const int m = blockIdx.x, vol = blockIdx.y, tid = threadIdx.x;
+template <int NLR, int NT>
+__global__ void __launch_bounds__(NT) finish_kernel(FinishArgs a) {
+    __shared__ uint32_t wsum[NT / 64][NLR];
+    const int vol = blockIdx.x, m = blockIdx.y, tid = threadIdx.x;
     const int K = a.K;
     int p, q, r;
     decode_moment(m, p, q, r);
     const int k = p + r;
-    uint64_t mask = a.slot_mask;
-    int ipt = a.ipt, tile0 = 0;
+    // The tiles of slots 0 .. 2k+1 (images d <= k) are the range [tbase, tbase + nent),
+    // slot by slot.  One volume: slot s owns [tile0[s], tile0[s+1]).  Batched ROI: each
+    // non-empty slot owns ipt tiles, in slot order.
+    uint32_t mask = 0;
+    int ipt = 0, nent;
+    size_t tbase = 0;
     if (a.rois) {
         const RoiDesc &rd = a.rois[vol];
-        mask = 0;
-        for (int s = 0; s < 14 && s < 2 * (K + 1); ++s)
-            if (rd.slot_len[s]) mask |= (uint64_t)1 << s;
+        for (int s = 0; s < 14 && s < 2 * (k + 1); ++s)
+            if (rd.slot_len[s]) mask |= 1u << s;
         ipt = (int)((rd.M + 15) / 16);
-        tile0 = rd.tile0;
+        tbase = (size_t)rd.tile0;
+        nent = __popc(mask) * ipt;
+    } else {
+        nent = a.tile0[2 * k + 2];
     }
     mw::Int<NLR> num;
     mw::set_zero(num);
-    const int per_d = 2 * ipt, nent = (k + 1) * per_d;
-    for (int e0 = tid; e0 < nent; e0 += FIN_BATCH * FIN_THREADS) {
+    for (int e0 = tid; e0 < nent; e0 += FIN_BATCH * NT) {
         mw::Int<NLR> v[FIN_BATCH];
         int64_t c[FIN_BATCH];
         // all loads of the batch first (coefficient and tile value are independent)
 #pragma unroll
         for (int b = 0; b < FIN_BATCH; ++b) {
-            const int e = e0 + b * FIN_THREADS;
-            const int d = e / per_d, rem = e - d * per_d;
-            const int side = rem / ipt, it = rem - side * ipt;
-            const int s = 2 * d + side;
+            const int e = e0 + b * NT;
             mw::set_zero(v[b]);
             c[b] = 0;
-            if (e < nent && ((mask >> s) & 1u)) {
+            if (e < nent) {
+                int s = 0;
+                if (a.rois) {
+                    // the (e / ipt)-th set bit of mask
+                    uint32_t mm = mask;
+                    for (int rank = e / ipt; rank > 0; --rank) mm &= mm - 1u;
+                    s = __ffs(mm) - 1;
+                } else {
+                    while (e >= a.tile0[s + 1]) ++s;
+                }
+                const int d = s >> 1, side = s & 1;
                 c[b] = (side == 0 && (k & 1)) ? -c_num[k][p][d] : c_num[k][p][d];
-                const int rank = __popcll(mask & (((uint64_t)1 << s) - 1u));
-                const size_t tile = (size_t)tile0 + (size_t)rank * ipt + it;
+                const size_t tile = tbase + (size_t)e;
                 const uint32_t *src = a.part + ((tile * (K + 1) + k) * (K + 1) + q) * NLR;
 #pragma unroll
                 for (int l = 0; l < NLR; ++l) v[b].w[l] = src[l];
@@ -92,12 +104,14 @@ __global__ void __launch_bounds__(FIN_THREADS) finish_kernel(FinishArgs a) {
         for (int l = 0; l < NLR; ++l) o.w[l] = (uint32_t)__shfl_xor((int)num.w[l], sh, 64);
         mw::add(num, o);
     }
-    if ((tid & 63) == 0)
+    if (NT > 64) {
+        if ((tid & 63) == 0)
 #pragma unroll
-        for (int l = 0; l < NLR; ++l) wsum[tid >> 6][l] = num.w[l];
-    __syncthreads();
+            for (int l = 0; l < NLR; ++l) wsum[tid >> 6][l] = num.w[l];
+        __syncthreads();
+    }
     if (tid != 0) return;
-    for (int w = 1; w < FIN_THREADS / 64; ++w) {
+    for (int w = 1; w < NT / 64; ++w) {
         mw::Int<NLR> o;
 #pragma unroll
         for (int l = 0; l < NLR; ++l) o.w[l] = wsum[w][l];
@@ -118,11 +132,17 @@ __global__ void __launch_bounds__(FIN_THREADS) finish_kernel(FinishArgs a) {
     }
 }
 
+template <int NLR>
+static void finish_go(const FinishArgs &a, dim3 grid, hipStream_t st) {
+    if (a.rois) hipLaunchKernelGGL((finish_kernel<NLR, FIN_THREADS_ROI>), grid, dim3(FIN_THREADS_ROI), 0, st, a);
+    else hipLaunchKernelGGL((finish_kernel<NLR, FIN_THREADS>), grid, dim3(FIN_THREADS), 0, st, a);
+}
+
 hipError_t launch_finish(int nlr, const FinishArgs &a, hipStream_t st) {
-    const dim3 grid(n_moments(a.K), a.nvol);
-    if (nlr == 4) hipLaunchKernelGGL((finish_kernel<4>), grid, dim3(FIN_THREADS), 0, st, a);
-    else if (nlr == 8) hipLaunchKernelGGL((finish_kernel<8>), grid, dim3(FIN_THREADS), 0, st, a);
-    else if (nlr == 12) hipLaunchKernelGGL((finish_kernel<12>), grid, dim3(FIN_THREADS), 0, st, a);
+    const dim3 grid(a.nvol, n_moments(a.K));  // volumes along x: no 65535 limit on batches
+    if (nlr == 4) finish_go<4>(a, grid, st);
+    else if (nlr == 8) finish_go<8>(a, grid, st);
+    else if (nlr == 12) finish_go<12>(a, grid, st);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }

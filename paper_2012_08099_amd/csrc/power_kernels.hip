@@ -31,28 +31,27 @@ struct TileInfo {
     const int32_t *base;  // row of the tile's first item, this slot
     int32_t ybase;      // y of item i of the tile: (ybase + i) / ydiv
     int32_t ydiv;
+    int32_t ks0, ks1;   // steps of 64 values of a covered by the tile
 };
 
 __device__ bool decode_tile(const PowerArgs &a, int tile, TileInfo &ti) {
     if (!a.rois) {
-        const int ipt = (a.nitems + 15) / 16;
-        int cnt = 0;
-        for (int s = 0; s <= 2 * a.K + 1; ++s) {
-            if (a.rl.slot_len[s] == 0) continue;
-            if (tile < cnt + ipt) {
-                const int item0 = (tile - cnt) * 16;
-                ti.slot = s;
-                ti.nitems = a.nitems - item0 < 16 ? a.nitems - item0 : 16;
-                ti.len = a.rl.slot_len[s];
-                ti.stride = a.rl.row_stride;
-                ti.base = a.rows + (int64_t)item0 * a.rl.row_stride + a.rl.slot_off[s];
-                ti.ybase = item0;
-                ti.ydiv = a.zsplits;
-                return true;
-            }
-            cnt += ipt;
-        }
-        return false;
+        if (tile >= a.rl.tile0[NSLOT]) return false;
+        int s = 0;
+        while (tile >= a.rl.tile0[s + 1]) ++s;  // empty slots own no tiles
+        const int local = tile - a.rl.tile0[s], nck = a.rl.nck[s];
+        const int blk = local / nck, ch = local - blk * nck;
+        const int item0 = blk * 16;
+        ti.slot = s;
+        ti.nitems = a.nitems - item0 < 16 ? a.nitems - item0 : 16;
+        ti.len = a.rl.slot_len[s];
+        ti.stride = a.rl.row_stride;
+        ti.base = a.rows + (int64_t)item0 * a.rl.row_stride + a.rl.slot_off[s];
+        ti.ybase = item0;
+        ti.ydiv = a.zsplits;
+        ti.ks0 = ch * a.rl.kchunk;
+        ti.ks1 = ti.ks0 + a.rl.kchunk < ti.len / 64 ? ti.ks0 + a.rl.kchunk : ti.len / 64;
+        return true;
     }
     const RoiDesc &rd = a.rois[a.tile_roi[tile]];
     const int ipt = (int)((rd.M + 15) / 16);
@@ -68,6 +67,8 @@ __device__ bool decode_tile(const PowerArgs &a, int tile, TileInfo &ti) {
             ti.base = a.rows + rd.row_base + (int64_t)item0 * rd.row_stride + rd.slot_off[s];
             ti.ybase = item0;
             ti.ydiv = 1;
+            ti.ks0 = 0;
+            ti.ks1 = ti.len / 64;
             return true;
         }
         cnt += ipt;
@@ -152,7 +153,6 @@ __global__ void __launch_bounds__(MW * 64) power_mfma_kernel(PowerArgs a) {
     const int il = lane & 15;
     const bool iv = il < ti.nitems;
     const int32_t *rp = ti.base + (iv ? (int64_t)il * ti.stride : 0) + (lane >> 4) * 16;
-    const int nks = ti.len / 64;
     const int nt = a.pow.nt;
     const uint4 *bt = a.pow.b + lane;
 
@@ -196,12 +196,12 @@ __global__ void __launch_bounds__(MW * 64) power_mfma_kernel(PowerArgs a) {
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int tp = 0; tp < PW_NTP; ++tp) acc[c][tp] = v4i{0, 0, 0, 0};
-        for (int ks0 = wave; ks0 < nks; ks0 += PW_PF * MW) {
+        for (int ks0 = ti.ks0 + wave; ks0 < ti.ks1; ks0 += PW_PF * MW) {
             uint4 rq[PW_PF][4], bq[PW_PF][PW_NTP];
 #pragma unroll
             for (int f = 0; f < PW_PF; ++f) {
                 const int ks = ks0 + f * MW;
-                const bool ok = ks < nks;
+                const bool ok = ks < ti.ks1;
                 const uint4 *p = reinterpret_cast<const uint4 *>(rp + ks * 64);
 #pragma unroll
                 for (int i = 0; i < 4; ++i) rq[f][i] = (ok && iv) ? p[i] : make_uint4(0u, 0u, 0u, 0u);
@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(MW * 64) power_mfma_kernel(PowerArgs a) {
             }
 #pragma unroll
             for (int f = 0; f < PW_PF; ++f) {
-                if (ks0 + f * MW >= nks) break;
+                if (ks0 + f * MW >= ti.ks1) break;
                 const uint32_t v[16] = {rq[f][0].x, rq[f][0].y, rq[f][0].z, rq[f][0].w,
                                         rq[f][1].x, rq[f][1].y, rq[f][1].z, rq[f][1].w,
                                         rq[f][2].x, rq[f][2].y, rq[f][2].z, rq[f][2].w,
@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_valu_kernel(PowerArgs a) 
         mw::Int<NLS> acc[KMAX + 1];
 #pragma unroll
         for (int k = 0; k <= KMAX; ++k) mw::set_zero(acc[k]);
-        for (int32_t aa = lane; aa < ti.len; aa += 64) {
+        for (int32_t aa = ti.ks0 * 64 + lane; aa < ti.ks1 * 64; aa += 64) {
             const uint32_t P = (uint32_t)rp[aa];
             if (P == 0u) continue;
             mw::Int<NLS> t;
