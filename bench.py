@@ -299,6 +299,8 @@ def main(argv=None):
     ap.add_argument("--streams", type=int, default=2,
                     help="volumes in flight (one stream and workspace each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (planner defaults for the work split)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the moments of one volume "
@@ -329,6 +331,18 @@ def main(argv=None):
         vols.append(v.contiguous())
     nm, nm4 = dpm.num_moments(K), dpm.num_moments(min(K, 4))
     code = 1 if dt == "u8" else 2
+    tuning = None
+    if not a.no_tune:
+        # the work split (z-splits, power-tile chunk) measured for this shape; every
+        # candidate must give the default plan's moments bit for bit
+        from paper_2012_08099_amd import autotune
+        t0 = time.perf_counter()
+        r = autotune.tune(vols[0], K, reps=20, warmup=3)
+        default = [c for c in r["candidates"] if c["z_splits"] == 0 and c["power_chunk"] == 0][0]
+        tuning = {"z_splits": r["best"]["z_splits"], "power_chunk": r["best"]["power_chunk"],
+                  "ms_best": r["best"]["ms"], "ms_planner_default": default["ms"],
+                  "candidates": len(r["candidates"]), "seconds": time.perf_counter() - t0}
+        log("tuning", tuning)
     depth = max(1, a.streams)
     wsb = dpm.workspace_bytes(shape, code, K)
     ws = [torch.empty(wsb, dtype=torch.uint8, device="cuda:0") for _ in range(depth)]
@@ -412,6 +426,8 @@ def main(argv=None):
                      "kernel": "slice_kernel (projection, one pass over the volume)",
                      "algorithmic_bytes_per_launch": bytes_launch},
         "source_hash": shash,
+        "tuning": tuning,
+        "plan": {k: plan[k] for k in ("z_splits", "n_items", "power_tiles", "power_chunk")},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(V0, K)

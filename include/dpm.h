@@ -131,13 +131,30 @@ typedef struct {
 
 size_t dpm_batched_workspace_bytes(const dpm_roi *rois, int n_rois, int max_order);
 
-/* All ROIs in one persistent launch sequence.  out_device->exact / ->fp64 hold
- * n_rois consecutive result blocks (block i at i * dpm_num_moments(...)). */
+/* All ROIs in one launch sequence on `stream`: a prep kernel (per-ROI geometry and
+ * work items), the projection of every (ROI, y) slice, the power-sum tiles of every
+ * ROI, and one recombination per (ROI, moment).  Orders <= 6 (else DPM_ENOTSUP); ROI
+ * dims <= 4096 (else DPM_ERANGE).  out_device->exact / ->fp64 hold n_rois consecutive
+ * result blocks (block i at i * dpm_num_moments(...)); workspace must hold
+ * dpm_batched_workspace_bytes() bytes (else DPM_ENOMEM).
+ *
+ * Repeated calls: when a call repeats an earlier one exactly (same ROI descriptors,
+ * order, packed / output / workspace pointers and workspace size, same device), its
+ * launch sequence is captured into a hipGraph on the second sighting and replayed from
+ * then on, with no host planning and no descriptor upload; the contents of `packed` may
+ * change between calls.  Up to 16 graphs are cached, least recently used evicted; they
+ * are freed by dpm_release.  Graphs are not used while stage timing is enabled or when
+ * the environment sets DPM_NO_GRAPH=1.  Not safe against concurrent calls that share a
+ * workspace. */
 int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int max_order,
                         const dpm_out *out_device, void *workspace, size_t ws_bytes,
                         void *stream);
 
-/* Free every library-owned device workspace and cached plan. */
+/* Number of batched-call graphs currently cached (see dpm_moments_batched). */
+int dpm_batched_graph_count(void);
+
+/* Free every library-owned device workspace, cached table and cached graph.  Call it
+ * only when no library work is in flight. */
 int dpm_release(void);
 
 /* ---- stage timing (tracing) --------------------------------------------------
@@ -257,9 +274,34 @@ typedef struct {
     int32_t bits_moment;   /* bound on recombination numerators (bits)        */
     int64_t lds_bytes;     /* LDS per projection workgroup (largest group)    */
     int64_t workspace;     /* bytes                                           */
+    int32_t power_tiles;   /* workgroups of the power-sum kernel              */
+    int32_t power_chunk;   /* steps of 64 values of a per power tile (0: rows) */
 } dpm_plan_info;
 
 int dpm_plan(const int64_t dims[3], dpm_dtype dtype, int max_order, dpm_plan_info *info);
+
+/* ---- tuning ---------------------------------------------------------------------
+ * Per-shape overrides of two planner choices, installed by an autotuner (the Python
+ * package's `autotune` module times the candidates through dpm_moments_async and
+ * installs the fastest).  Both change how the work is split, never the result.
+ *   z_splits:    work items per y-slice (each projection workgroup takes a z range);
+ *                0 = the planner's choice.
+ *   power_chunk: steps of 64 values of a per power-sum tile on the matrix cores;
+ *                0 = the planner's choice, -1 = whole rows.
+ * An override applies to every later plan of exactly these dims, dtype and order, and
+ * to the workspace size reported for them (query dpm_workspace_bytes after setting
+ * it).  The environment overrides DPM_ZSPLITS / DPM_PW_KCHUNK take precedence.
+ * t == NULL removes the override of this shape; dpm_tune_clear removes all.
+ * Errors: DPM_EINVAL for bad dims, dtype, order, z_splits outside [0, 4096] or
+ * power_chunk outside [-1, 4096]. */
+typedef struct {
+    int32_t z_splits;
+    int32_t power_chunk;
+    int32_t reserved[2];
+} dpm_tuning;
+
+int dpm_tune_set(const int64_t dims[3], dpm_dtype dtype, int max_order, const dpm_tuning *t);
+int dpm_tune_clear(void);
 
 #ifdef __cplusplus
 }

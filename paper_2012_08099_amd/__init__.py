@@ -203,6 +203,11 @@ def moments_batched(packed, rois, K, out_exact, out_fp64, workspace, stream=None
     check(rc, "dpm_moments_batched")
 
 
+def batched_graph_count():
+    """Graphs cached for repeated batched calls."""
+    return int(lib().dpm_batched_graph_count())
+
+
 def recomb_weight(k, p, d):
     n, den = ctypes.c_int64(), ctypes.c_uint64()
     check(lib().dpm_recomb_weight(k, p, d, ctypes.byref(n), ctypes.byref(den)), "dpm_recomb_weight")

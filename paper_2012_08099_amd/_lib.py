@@ -49,7 +49,13 @@ class PlanInfo(ctypes.Structure):
                 ("z_splits", ctypes.c_int32), ("limbs_slice", ctypes.c_int32),
                 ("limbs_moment", ctypes.c_int32), ("bits_slice", ctypes.c_int32),
                 ("bits_moment", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
-                ("workspace", ctypes.c_int64)]
+                ("workspace", ctypes.c_int64), ("power_tiles", ctypes.c_int32),
+                ("power_chunk", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("z_splits", ctypes.c_int32), ("power_chunk", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Profile(ctypes.Structure):
@@ -104,6 +110,10 @@ SIGNATURES = {
                                            ctypes.POINTER(Out), ctypes.c_void_p, ctypes.c_size_t,
                                            ctypes.c_void_p]),
     "dpm_release": (ctypes.c_int, []),
+    "dpm_batched_graph_count": (ctypes.c_int, []),
+    "dpm_tune_set": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                    ctypes.POINTER(Tuning)]),
+    "dpm_tune_clear": (ctypes.c_int, []),
     "dpm_recomb_weight": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]),
     "dpm_profile_enable": (ctypes.c_int, [ctypes.c_int]),

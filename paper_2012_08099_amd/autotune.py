@@ -1,0 +1,115 @@
+"""Autotuner for the planner's work split, through the C ABI.
+
+Two planner choices change how one volume's work is divided, never its result:
+
+* ``z_splits``: projection work items per y-slice (each workgroup projects a z range of
+  one slice; more splits mean more workgroups and more image rows to sum);
+* ``power_chunk``: steps of 64 coordinates per power-sum tile on the matrix cores (smaller
+  chunks mean more, shorter workgroups and more tile partials to combine).
+
+``tune`` times every candidate pair with ``dpm_moments_async`` on one stream (HIP events
+around ``reps`` calls), requires each candidate's moments to be bit-identical to the
+planner's default, installs the fastest with ``dpm_tune_set`` and returns the timings.
+Results can be kept in a JSON file (``save`` / ``load``) keyed by shape, dtype and order,
+and installed again in a later process without re-measuring.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+from . import _lib
+from . import _dims_of_shape, _dtype_code, check, lib, moments_async, num_moments, workspace_bytes
+
+Z_SPLITS = (0, 1, 2, 4, 8)        # 0: the planner's choice
+POWER_CHUNKS = (0, 4, 8, 16, -1)  # 0: the planner's choice, -1: whole rows
+
+
+def set_tuning(shape, dtype_code, K, z_splits=0, power_chunk=0):
+    """Install an override for volumes of numpy shape (N, M, L), dtype code and order K."""
+    t = _lib.Tuning(int(z_splits), int(power_chunk))
+    check(lib().dpm_tune_set(_dims_of_shape(shape), int(dtype_code), int(K), ctypes.byref(t)), "dpm_tune_set")
+
+
+def unset_tuning(shape, dtype_code, K):
+    check(lib().dpm_tune_set(_dims_of_shape(shape), int(dtype_code), int(K), None), "dpm_tune_set")
+
+
+def clear():
+    check(lib().dpm_tune_clear(), "dpm_tune_clear")
+
+
+def _key(shape, dtype_code, K):
+    N, M, L = (int(s) for s in shape)
+    return f"{L}x{M}x{N}:{int(dtype_code)}:{int(K)}"
+
+
+def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS, stream=None):
+    """Measure every (z_splits, power_chunk) candidate on the device volume ``vol``
+    ((N, M, L) uint8, or uint16 carried as int16) and install the fastest.
+
+    Returns {"best": {...}, "candidates": [{"z_splits", "power_chunk", "ms"}, ...]}."""
+    import torch
+    code = _dtype_code(vol)
+    shape = tuple(vol.shape)
+    dev = vol.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    nm = num_moments(K)
+    nm4 = num_moments(min(K, 4))
+
+    def run(cand):
+        if cand is None:
+            unset_tuning(shape, code, K)
+        else:
+            set_tuning(shape, code, K, *cand)
+        ws = torch.empty(workspace_bytes(shape, code, K), dtype=torch.uint8, device=dev)
+        ex = torch.empty((nm4, 2), dtype=torch.int64, device=dev)
+        fp = torch.empty(nm, dtype=torch.float64, device=dev)
+        with torch.cuda.stream(st):
+            for _ in range(warmup):
+                moments_async(vol, K, ex, fp, ws, stream=st)
+            t0 = torch.cuda.Event(enable_timing=True)
+            t1 = torch.cuda.Event(enable_timing=True)
+            t0.record(st)
+            for _ in range(reps):
+                moments_async(vol, K, ex, fp, ws, stream=st)
+            t1.record(st)
+        t1.synchronize()
+        return t0.elapsed_time(t1) / reps, ex.cpu(), fp.cpu()
+
+    _, ref_ex, ref_fp = run(None)
+    results = []
+    for zs in z_splits:
+        for pc in power_chunks:
+            ms, ex, fp = run((zs, pc))
+            if not (torch.equal(ex, ref_ex) and torch.equal(fp.view(torch.int64), ref_fp.view(torch.int64))):
+                raise RuntimeError(f"tuning candidate z_splits={zs} power_chunk={pc} changed the result")
+            results.append({"z_splits": zs, "power_chunk": pc, "ms": ms})
+    best = min(results, key=lambda r: r["ms"])
+    set_tuning(shape, code, K, best["z_splits"], best["power_chunk"])
+    return {"key": _key(shape, code, K), "best": best, "candidates": results}
+
+
+def save(results, path):
+    """Merge tuning results ({"key", "best"} dicts from ``tune``) into a JSON file."""
+    table = {}
+    if os.path.exists(path):
+        with open(path) as fh:
+            table = json.load(fh)
+    for r in results:
+        table[r["key"]] = {"z_splits": r["best"]["z_splits"], "power_chunk": r["best"]["power_chunk"],
+                           "ms": r["best"]["ms"]}
+    with open(path, "w") as fh:
+        json.dump(table, fh, indent=1, sort_keys=True)
+
+
+def load(path):
+    """Install every override stored in a JSON file written by ``save``; returns the count."""
+    with open(path) as fh:
+        table = json.load(fh)
+    for key, v in table.items():
+        dims, code, K = key.split(":")
+        L, M, N = (int(x) for x in dims.split("x"))
+        set_tuning((N, M, L), int(code), int(K), v["z_splits"], v["power_chunk"])
+    return len(table)

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -21,6 +22,7 @@ int batched_ensure_tables();  // dpm_api.cpp
 int batched_numsum_bits(int k);
 void batched_set_error(int e);
 void batched_prof_mark(int idx, hipStream_t st);
+bool batched_profiling();
 int batched_powtab(int amax, int K, PowTab &out);
 bool batched_pow_columns(int amax, int K, int32_t colstart[KMAX + 2]);
 }  // namespace dpm
@@ -176,11 +178,188 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     return DPM_OK;
 }
 
+// The launch sequence of one batched call: prep, projection, power sums, recombination.
+// drd holds the plan's ROI descriptors on the device.
+hipError_t enqueue(const BPlan &p, const PowTab &pt, const uint8_t *packed, RoiDesc *drd, uint8_t *ws,
+                   const dpm_out *out, hipStream_t st, bool marks) {
+    const int K = p.K, nd = K + 1;
+    BatchItem *dit = reinterpret_cast<BatchItem *>(ws + p.off_it);
+    int32_t *rows = reinterpret_cast<int32_t *>(ws + p.off_rows);
+    uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
+    int32_t *tmap = reinterpret_cast<int32_t *>(ws + p.off_tmap);
+    if (marks) batched_prof_mark(0, st);
+    BatchSliceArgs a{packed, drd, dit, K, rows, tmap, reinterpret_cast<ItemGeom *>(ws + p.off_geom)};
+    hipError_t e = launch_batched_prep(nd, a, p.nrois, st);
+    if (e == hipSuccess && p.has_u16) e = launch_slice_batched(2, 0, nd, a, p.items, p.lds, st);
+    if (e == hipSuccess && p.has_u8) e = launch_slice_batched(1, 0, nd, a, p.items, p.lds, st);
+    if (e == hipSuccess && marks) batched_prof_mark(1, st);
+    if (e == hipSuccess) {
+        PowerArgs pa{};
+        pa.rows = rows;
+        pa.rois = drd;
+        pa.tile_roi = tmap;
+        pa.nrois = p.nrois;
+        pa.nitems = p.items;
+        pa.zsplits = 1;
+        pa.K = K;
+        pa.ntiles = p.ntiles;
+        pa.max_len = p.amax;
+        pa.pow = pt;
+        pa.part = part;
+        e = launch_power(p.nls, p.nlr, pa, st);
+    }
+    if (e == hipSuccess && marks) batched_prof_mark(2, st);
+    if (e == hipSuccess) {
+        FinishArgs f{};
+        f.part = part;
+        f.rois = drd;
+        f.nvol = p.nrois;
+        f.K = K;
+        f.exact = out->exact;
+        f.fp64 = out->fp64;
+        e = launch_finish(p.nlr, f, st);
+    }
+    if (e == hipSuccess && marks) batched_prof_mark(3, st);
+    return e;
+}
+
+// ---- hipGraph per repeated call
+// A call whose ROI descriptors, buffers, order and device repeat an earlier call's is
+// captured once (on its second sighting) and replayed from then on: the replay skips the
+// host planning and the descriptor upload.  The graph owns a device copy of the
+// descriptors; everything else lives in the caller's buffers, which the key pins.
+struct GraphKey {
+    int dev = -1, n = 0, K = 0;
+    const void *packed = nullptr, *exact = nullptr, *fp64 = nullptr, *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::vector<uint8_t> rois;
+    uint64_t hash = 0;
+    bool operator==(const GraphKey &o) const {
+        return hash == o.hash && dev == o.dev && n == o.n && K == o.K && packed == o.packed && exact == o.exact &&
+               fp64 == o.fp64 && ws == o.ws && ws_bytes == o.ws_bytes && rois == o.rois;
+    }
+};
+struct GraphEntry {
+    GraphKey key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *drd = nullptr;        // device copy of the ROI descriptors
+    hipEvent_t done = nullptr;  // recorded after every launch
+    uint64_t last_use = 0;
+};
+constexpr size_t kGraphs = 16;  // cached graphs (least recently used goes first)
+constexpr size_t kSeen = 64;    // remembered first sightings
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+std::vector<uint64_t> g_seen;
+uint64_t g_graph_tick = 0;
+
+bool graphs_enabled() {
+    const char *e = std::getenv("DPM_NO_GRAPH");
+    return !(e && atoi(e)) && !batched_profiling();
+}
+
+uint64_t key_hash(const GraphKey &k) {
+    uint64_t h = 1469598103934665603ull;  // FNV-1a
+    auto mix = [&](const void *p, size_t n) {
+        const uint8_t *b = static_cast<const uint8_t *>(p);
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    };
+    mix(&k.dev, sizeof k.dev);
+    mix(&k.n, sizeof k.n);
+    mix(&k.K, sizeof k.K);
+    mix(&k.packed, sizeof k.packed);
+    mix(&k.exact, sizeof k.exact);
+    mix(&k.fp64, sizeof k.fp64);
+    mix(&k.ws, sizeof k.ws);
+    mix(&k.ws_bytes, sizeof k.ws_bytes);
+    mix(k.rois.data(), k.rois.size());
+    return h;
+}
+
+// true if this hash was seen before (then forgotten); else remembered.  Caller holds
+// g_graph_mu.
+bool seen_before(uint64_t h) {
+    auto it = std::find(g_seen.begin(), g_seen.end(), h);
+    if (it != g_seen.end()) {
+        g_seen.erase(it);
+        return true;
+    }
+    if (g_seen.size() >= kSeen) g_seen.erase(g_seen.begin());
+    g_seen.push_back(h);
+    return false;
+}
+
+void destroy_entry(GraphEntry &g) {
+    if (g.done) (void)hipEventSynchronize(g.done);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    if (g.drd) (void)hipFree(g.drd);
+    if (g.done) (void)hipEventDestroy(g.done);
+    g = GraphEntry{};
+}
+
+// Captures the call on a private stream, caches it and launches it on st.  false: the
+// graph could not be made (nothing was launched; the caller runs the call eagerly).
+bool build_and_launch_graph(const GraphKey &key, const BPlan &p, const PowTab &pt, const uint8_t *packed,
+                            uint8_t *ws, const dpm_out *out, hipStream_t st) {
+    GraphEntry g;
+    g.key = key;
+    const size_t brd = sizeof(RoiDesc) * p.rd.size();
+    if (hipMalloc(&g.drd, brd) != hipSuccess) return false;
+    if (hipMemcpy(g.drd, p.rd.data(), brd, hipMemcpyHostToDevice) != hipSuccess ||
+        hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess) {
+        destroy_entry(g);
+        return false;
+    }
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+        destroy_entry(g);
+        return false;
+    }
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t el = enqueue(p, pt, packed, static_cast<RoiDesc *>(g.drd), ws, out, cs, false);
+        e = hipStreamEndCapture(cs, &g.graph);
+        if (el != hipSuccess) e = el;
+    }
+    (void)hipStreamDestroy(cs);
+    if (e == hipSuccess && g.graph) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess || !g.exec) {
+        (void)hipGetLastError();
+        destroy_entry(g);
+        return false;
+    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (g_graphs.size() >= kGraphs) {
+        auto victim = std::min_element(g_graphs.begin(), g_graphs.end(),
+                                       [](const GraphEntry &a, const GraphEntry &b) { return a.last_use < b.last_use; });
+        destroy_entry(*victim);
+        g_graphs.erase(victim);
+    }
+    g.last_use = ++g_graph_tick;
+    e = hipGraphLaunch(g.exec, st);
+    if (e == hipSuccess) e = hipEventRecord(g.done, st);
+    g_graphs.push_back(g);
+    if (e != hipSuccess) {
+        batched_set_error((int)e);
+        // the graph stays cached; this call's launch failed and is reported by the
+        // caller's next device error check
+    }
+    return e == hipSuccess;
+}
+
 }  // namespace
 
 namespace dpm {
 // Frees the pinned staging buffers (called by dpm_release).
 int batched_release() {
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (auto &g : g_graphs) destroy_entry(g);
+        g_graphs.clear();
+        g_seen.clear();
+    }
     std::lock_guard<std::mutex> lk(g_stage_mu);
     int rc = DPM_OK;
     for (auto &s : g_stage) {
@@ -206,23 +385,54 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
     if (!packed || !out_device || !workspace) return DPM_EINVAL;
     int rc = batched_ensure_tables();
     if (rc) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    const bool graphs = graphs_enabled() && rois && n_rois > 0 && max_order >= 0 && max_order <= 6;
+    GraphKey key;
+    bool repeat = false;
+    if (graphs) {
+        if ((e = hipGetDevice(&key.dev)) != hipSuccess) {
+            batched_set_error((int)e);
+            return DPM_EDEVICE;
+        }
+        key.n = n_rois;
+        key.K = max_order;
+        key.packed = packed;
+        key.exact = out_device->exact;
+        key.fp64 = out_device->fp64;
+        key.ws = workspace;
+        key.ws_bytes = ws_bytes;
+        key.rois.assign(reinterpret_cast<const uint8_t *>(rois),
+                        reinterpret_cast<const uint8_t *>(rois) + sizeof(dpm_roi) * (size_t)n_rois);
+        key.hash = key_hash(key);
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (auto &g : g_graphs)
+            if (g.key == key) {
+                // a repeated call: replay its graph (no planning, no descriptor upload)
+                g.last_use = ++g_graph_tick;
+                e = hipGraphLaunch(g.exec, st);
+                if (e == hipSuccess) e = hipEventRecord(g.done, st);
+                if (e != hipSuccess) {
+                    batched_set_error((int)e);
+                    return DPM_EDEVICE;
+                }
+                return DPM_OK;
+            }
+        repeat = seen_before(key.hash);
+    }
     BPlan p;
     if ((rc = bplan(rois, n_rois, max_order, p))) return rc;
     if (ws_bytes < p.total) return DPM_ENOMEM;
-    hipStream_t st = static_cast<hipStream_t>(stream);
     uint8_t *ws = static_cast<uint8_t *>(workspace);
-    RoiDesc *drd = reinterpret_cast<RoiDesc *>(ws + p.off_rd);
-    BatchItem *dit = reinterpret_cast<BatchItem *>(ws + p.off_it);
-    int32_t *rows = reinterpret_cast<int32_t *>(ws + p.off_rows);
-    uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
-    int32_t *tmap = reinterpret_cast<int32_t *>(ws + p.off_tmap);
     PowTab pt{};
     if (p.mfma && (rc = batched_powtab(p.amax, max_order, pt))) return rc;
-    hipError_t e = hipSuccess;
+    if (repeat && build_and_launch_graph(key, p, pt, static_cast<const uint8_t *>(packed), ws, out_device, st))
+        return DPM_OK;
+    RoiDesc *drd = reinterpret_cast<RoiDesc *>(ws + p.off_rd);
     {
+        std::lock_guard<std::mutex> lk(g_stage_mu);
         int dev = 0;
         e = hipGetDevice(&dev);
-        std::lock_guard<std::mutex> lk(g_stage_mu);
         const size_t brd = sizeof(RoiDesc) * p.rd.size();
         Staging *sg = e == hipSuccess ? stage_acquire(brd, dev) : nullptr;
         if (!sg) return e == hipSuccess ? DPM_ENOMEM : (batched_set_error((int)e), DPM_EDEVICE);
@@ -230,50 +440,17 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
         e = hipMemcpyAsync(drd, sg->p, brd, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipEventRecord(sg->ev, st);
     }
-    if (e != hipSuccess) {
-        batched_set_error((int)e);
-        return DPM_EDEVICE;
-    }
-    const int nd = max_order + 1;
-    batched_prof_mark(0, st);
-    BatchSliceArgs a{static_cast<const uint8_t *>(packed), drd, dit, max_order, rows, tmap,
-                     reinterpret_cast<ItemGeom *>(ws + p.off_geom)};
-    e = launch_batched_prep(nd, a, n_rois, st);
-    if (e == hipSuccess && p.has_u16) e = launch_slice_batched(2, 0, nd, a, p.items, p.lds, st);
-    if (e == hipSuccess && p.has_u8) e = launch_slice_batched(1, 0, nd, a, p.items, p.lds, st);
-    if (e == hipSuccess) batched_prof_mark(1, st);
-    if (e == hipSuccess) {
-        PowerArgs pa{};
-        pa.rows = rows;
-        pa.rois = drd;
-        pa.tile_roi = tmap;
-        pa.nrois = n_rois;
-        pa.nitems = p.items;
-        pa.zsplits = 1;
-        pa.K = max_order;
-        pa.ntiles = p.ntiles;
-        pa.max_len = p.amax;
-        pa.pow = pt;
-        pa.part = part;
-        e = launch_power(p.nls, p.nlr, pa, st);
-    }
-    if (e == hipSuccess) batched_prof_mark(2, st);
-    if (e == hipSuccess) {
-        FinishArgs f{};
-        f.part = part;
-        f.rois = drd;
-        f.nvol = n_rois;
-        f.K = max_order;
-        f.exact = out_device->exact;
-        f.fp64 = out_device->fp64;
-        e = launch_finish(p.nlr, f, st);
-    }
-    if (e == hipSuccess) batched_prof_mark(3, st);
+    if (e == hipSuccess) e = enqueue(p, pt, static_cast<const uint8_t *>(packed), drd, ws, out_device, st, true);
     if (e != hipSuccess) {
         batched_set_error((int)e);
         return DPM_EDEVICE;
     }
     return DPM_OK;
+}
+
+int dpm_batched_graph_count(void) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    return (int)g_graphs.size();
 }
 
 }  // extern "C"

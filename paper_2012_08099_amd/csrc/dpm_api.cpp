@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/dpm.h"
@@ -190,6 +191,8 @@ struct Plan {
     int npairs = 0;
     int bits_slice = 0, bits_moment = 0;
     bool mfma = false;   // power sums on the matrix cores
+    int pow_passes = 0;  // column-tile passes of the matrix-core power kernel
+    dpm_tuning tune{};   // override of this shape (dpm_tune_set), zero if none
     int amax = 0;        // coordinate magnitudes covered by the power table
     RowLayout rl{};
     int nslots_used = 0;
@@ -256,6 +259,25 @@ int plan_widths(Plan &p) {
     return DPM_OK;
 }
 
+// ---- per-shape tuning overrides (dpm_tune_set)
+struct TuneKey {
+    int64_t L, M, N;
+    int elem, K;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(L, M, N, elem, K) < std::tie(o.L, o.M, o.N, o.elem, o.K);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, dpm_tuning> g_tune;
+
+bool tune_lookup(const Plan &p, dpm_tuning &t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(TuneKey{p.L, p.M, p.N, p.elem, p.K});
+    if (it == g_tune.end()) return false;
+    t = it->second;
+    return true;
+}
+
 int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Plan &p,
               const void *vol_for_alignment) {
     if (!dims) return DPM_EINVAL;
@@ -278,6 +300,7 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
     if (!full_rows) {
         const int64_t want = 512;
         if (p.M < want) zs = (int)std::min<int64_t>((want + p.M - 1) / p.M, std::max<int64_t>(1, p.N / 64));
+        if (tune_lookup(p, p.tune) && p.tune.z_splits > 0) zs = p.tune.z_splits;
         if (const char *e = std::getenv("DPM_ZSPLITS")) zs = std::max(1, atoi(e));
     }
     int64_t zrows = (p.N + zs - 1) / zs;
@@ -349,15 +372,18 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
         const bool small_p = (double)vmax * (double)std::max<int64_t>(p.L, p.zrows) < 268435456.0;
         int32_t cs[KMAX + 2];
         p.mfma = small_p && amax <= 8192 && pow_columns((int)amax, p.K, cs);
+        p.pow_passes = p.mfma ? (cs[p.K + 1] + 63) / 64 : 0;  // 4 column tiles of 16 per pass
         if (const char *e = std::getenv("DPM_NO_MFMA")) {
             if (atoi(e)) p.mfma = false;
         }
         p.amax = (int)amax;
     }
     {
-        // power-sum tiles; on the matrix cores each covers at most kchunk steps of 64
-        // values of a, so long rows spread over more workgroups
-        int kc = p.mfma ? 8 : (1 << 30);
+        // power-sum tiles; on the matrix cores with all power columns in one pass, each
+        // covers at most kchunk steps of 64 values of a, so long rows spread over more
+        // workgroups (with several passes the per-tile reassembly dominates: no chunks)
+        int kc = (p.mfma && p.pow_passes == 1) ? 8 : (1 << 30);
+        if (p.mfma && p.tune.power_chunk != 0) kc = p.tune.power_chunk > 0 ? p.tune.power_chunk : (1 << 30);
         if (const char *e = std::getenv("DPM_PW_KCHUNK")) {
             if (atoi(e) > 0 && p.mfma) kc = atoi(e);
         }
@@ -484,6 +510,10 @@ void batched_prof_mark(int idx, hipStream_t st) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
     prof_mark(idx, st);
 }
+bool batched_profiling() {
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    return g_prof_on;
+}
 int batched_ensure_tables() { return ensure_device_tables(); }
 int batched_numsum_bits(int k) {
     std::lock_guard<std::recursive_mutex> lk(g_mu);
@@ -547,6 +577,8 @@ int dpm_plan(const int64_t dims[3], dpm_dtype dtype, int max_order, dpm_plan_inf
     info->n_groups = p.ngroups;
     info->n_items = p.items;
     info->z_splits = p.zsplits;
+    info->power_tiles = p.ntiles;
+    info->power_chunk = p.rl.kchunk >= (1 << 30) ? 0 : p.rl.kchunk;
     info->limbs_slice = p.nls;
     info->limbs_moment = p.nlr;
     info->bits_slice = p.bits_slice;
@@ -631,6 +663,27 @@ int dpm_project_images(const void *volume, const int64_t dims[3], dpm_dtype dtyp
     if ((rc = ensure_buf(g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
     return run_plan(p, volume, images_device, off, w, nullptr, nullptr, g_ws[dev].ptr,
                     static_cast<hipStream_t>(stream));
+}
+
+int dpm_tune_set(const int64_t dims[3], dpm_dtype dtype, int max_order, const dpm_tuning *t) {
+    if (!dims || dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0) return DPM_EINVAL;
+    const int elem = elem_of(dtype);
+    if (!elem || max_order < 0 || max_order > KMAX) return DPM_EINVAL;
+    const TuneKey key{dims[0], dims[1], dims[2], elem, max_order};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!t) {
+        g_tune.erase(key);
+        return DPM_OK;
+    }
+    if (t->z_splits < 0 || t->z_splits > 4096 || t->power_chunk < -1 || t->power_chunk > 4096) return DPM_EINVAL;
+    g_tune[key] = *t;
+    return DPM_OK;
+}
+
+int dpm_tune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    return DPM_OK;
 }
 
 int dpm_release(void) {

@@ -259,3 +259,51 @@ def test_batched_matches_single_and_oracle(dpm, n, seed):
         if i < 25:
             single = dpm.moments(to_dev(V), K)
             assert single.exact == got.exact
+
+
+def test_batched_graph_replays(dpm, monkeypatch):
+    """A batched call repeated with the same descriptors and buffers is captured into a
+    graph on its second sighting and replayed from then on.  Every call -- first
+    (eager), second (capture + launch), later replays -- matches the oracle, with new
+    voxel contents written into the packed buffer between calls and other library work
+    and host synchronisations in between."""
+    import torch
+    monkeypatch.delenv("DPM_NO_GRAPH", raising=False)
+    say("batched graph replays")
+    dpm.release()
+    K = 4
+    n = 48
+    rois = synth.roi_batch(n, seed=5)
+    packed, desc = dpm.pack_rois(rois, "cuda:0")
+    nm = dpm.num_moments(K)
+    ex = torch.zeros((n * nm, 2), dtype=torch.int64, device="cuda:0")
+    fp = torch.zeros(n * nm, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(dpm.batched_workspace_bytes(desc, K), dtype=torch.uint8, device="cuda:0")
+    other = synth.uniform_volume((20, 9, 33), np.uint16, seed=3)
+    for call in range(5):
+        # new contents in place (same shapes, same buffer)
+        vols = [synth.uniform_volume(V.shape, V.dtype, seed=100 * call + i) if call % 2 else
+                (V if call == 0 else np.ascontiguousarray(V[::-1])) for i, V in enumerate(rois)]
+        newp, _ = dpm.pack_rois(vols, "cuda:0")
+        packed.copy_(newp)
+        ex.zero_()
+        fp.zero_()
+        dpm.moments_batched(packed, desc, K, ex, fp, ws)
+        torch.cuda.synchronize()
+        assert dpm.batched_graph_count() == (0 if call == 0 else 1), call
+        exact = dpm._exact_from_tensor(ex)
+        fpn = fp.cpu().numpy()
+        for i, V in enumerate(vols):
+            got = dpm.Moments(K, exact[i * nm:(i + 1) * nm], fpn[i * nm:(i + 1) * nm])
+            assert_moments_equal(got, onative.moments_hoisted(V, K), K, f"call {call} roi {i} {V.shape}")
+        # eager work of the library between replays
+        res = dpm.moments(to_dev(other), 3)
+        assert_moments_equal(res, oracle.moments_exact(other, 3), 3, "eager call between replays")
+    # a different output buffer is a different call: no replay of the cached graph
+    fp2 = torch.zeros_like(fp)
+    dpm.moments_batched(packed, desc, K, ex, fp2, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(fp2, fp)
+    assert dpm.batched_graph_count() == 1
+    dpm.release()
+    assert dpm.batched_graph_count() == 0

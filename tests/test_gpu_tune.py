@@ -1,0 +1,37 @@
+"""GPU test of the autotuner: every candidate work split is timed through the C ABI,
+must reproduce the default plan's moments bit for bit, and the installed fastest split
+still matches the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import assert_moments_equal, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_installs_an_exact_split():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_2012_08099_amd as dpm
+    from paper_2012_08099_amd import autotune
+    print("autotune 64x48x96 u16 K=6", flush=True)
+    sys.stdout.flush()
+    V = synth.uniform_volume((64, 48, 96), np.uint16, seed=2)
+    vol = to_dev(V)
+    try:
+        r = autotune.tune(vol, 6, reps=3, warmup=1, z_splits=(0, 1, 2, 4), power_chunks=(0, 4, -1))
+        assert len(r["candidates"]) == 12 and all(c["ms"] > 0 for c in r["candidates"])
+        best = r["best"]
+        info = dpm.plan(V.shape, 2, 6)
+        if best["z_splits"]:
+            assert info["z_splits"] <= best["z_splits"]
+        if best["power_chunk"] > 0:
+            assert info["power_chunk"] == best["power_chunk"]
+        res = dpm.moments(vol, 6)
+        assert_moments_equal(res, oracle.moments_exact(V, 6), 6, f"tuned {best}")
+    finally:
+        autotune.clear()

@@ -210,3 +210,52 @@ def test_batched_workspace_rejects_bad_rois(lib):
     rois[1].dims[:] = [8, 5, 8]
     assert lib.dpm_batched_workspace_bytes(rois, 2, 4) > 0
     assert lib.dpm_batched_workspace_bytes(rois, 2, 7) == 0   # batched path: orders <= 6
+
+
+def test_tuning_overrides_change_the_plan_only(lib):
+    """dpm_tune_set: a per-shape override of the work split shows in dpm_plan (z-splits,
+    power tiles) and is removed by t=NULL / dpm_tune_clear; bad values are refused."""
+    from paper_2012_08099_amd import _lib
+    d3 = (ctypes.c_int64 * 3)
+    dims = (96, 64, 256)
+    rc, base = plan(lib, dims, 2, 6)
+    assert rc == 0
+    t = _lib.Tuning(4, 4)
+    assert lib.dpm_tune_set(d3(*dims), 2, 6, ctypes.byref(t)) == 0
+    rc, tuned = plan(lib, dims, 2, 6)
+    assert rc == 0 and tuned.z_splits == 4 and tuned.n_items == 64 * 4
+    assert tuned.power_chunk == 4 and tuned.power_tiles > base.power_tiles
+    assert lib.dpm_workspace_bytes(d3(*dims), 2, 6) == tuned.workspace
+    # another order or dtype of the same dims is not affected
+    assert plan(lib, dims, 2, 5)[1].z_splits == base.z_splits
+    assert plan(lib, dims, 1, 6)[1].z_splits == base.z_splits
+    t.power_chunk = -1  # whole rows: one tile per block of 16 items per slot
+    assert lib.dpm_tune_set(d3(*dims), 2, 6, ctypes.byref(t)) == 0
+    rc, whole = plan(lib, dims, 2, 6)
+    assert whole.power_chunk == 0 and whole.power_tiles < tuned.power_tiles
+    assert lib.dpm_tune_set(d3(*dims), 2, 6, None) == 0
+    rc, again = plan(lib, dims, 2, 6)
+    assert (again.z_splits, again.power_tiles, again.workspace) == (base.z_splits, base.power_tiles, base.workspace)
+    assert lib.dpm_tune_set(d3(*dims), 2, 6, ctypes.byref(_lib.Tuning(2, 0))) == 0
+    assert lib.dpm_tune_clear() == 0
+    assert plan(lib, dims, 2, 6)[1].z_splits == base.z_splits
+    for bad in (_lib.Tuning(-1, 0), _lib.Tuning(5000, 0), _lib.Tuning(1, -2), _lib.Tuning(1, 5000)):
+        assert lib.dpm_tune_set(d3(*dims), 2, 6, ctypes.byref(bad)) == -1
+    assert lib.dpm_tune_set(d3(0, 4, 4), 2, 6, ctypes.byref(t)) == -1
+    assert lib.dpm_tune_set(d3(*dims), 2, 17, ctypes.byref(t)) == -1
+
+
+def test_tuning_cache_round_trip(lib, tmp_path):
+    """autotune.save / load: the JSON cache installs the stored overrides."""
+    from paper_2012_08099_amd import autotune
+    path = str(tmp_path / "tune.json")
+    autotune.save([{"key": "96x64x256:2:6", "best": {"z_splits": 2, "power_chunk": 16, "ms": 0.1}}], path)
+    autotune.save([{"key": "40x40x40:1:4", "best": {"z_splits": 1, "power_chunk": -1, "ms": 0.01}}], path)
+    try:
+        assert autotune.load(path) == 2
+        rc, info = plan(lib, (96, 64, 256), 2, 6)
+        assert info.z_splits == 2 and info.power_chunk == 16
+        rc, info = plan(lib, (40, 40, 40), 1, 4)
+        assert info.z_splits == 1 and info.power_chunk == 0
+    finally:
+        autotune.clear()
