@@ -15,6 +15,8 @@
 // accumulation over a are exact; the four waves split the contraction, and the limb-pair
 // sums are reassembled into the exact r with shifts.
 // VALU path (row values >= 2^28): multiword products and an exact lane reduction.
+#include <cstdlib>
+
 #include "dpm_common.h"
 #include "kernels.h"
 #include "mw.h"
@@ -128,63 +130,119 @@ __device__ __forceinline__ void yweight_store(const PowerArgs &a, const TileInfo
     }
 }
 
-// One workgroup per tile (16 items x one slot).  The MW waves split the K-steps of 64
-// coordinates (wave w takes steps w, w + MW, ...), loading PW_PF steps at once; their
-// int32 limb-pair sums meet in LDS; then every thread reassembles one (item, k) sum.
-// Long rows take four waves; short rows (a few K-steps, as in batches of small volumes)
-// take one, which then needs no LDS clearing or atomics and reassembles one 16-column
-// tile at a time.
-constexpr int PW_MW = 4;   // waves of the matrix-core kernel for long rows
+// One workgroup per tile (16 items x one slot).  Matrix-core kernels, three ways to
+// spread a tile over its waves:
+//  * split contraction (MW = 4): the waves split the K-steps of 64 coordinates (wave w
+//    takes steps w, w + 4, ...); their int32 limb-pair sums meet in LDS through atomics;
+//    up to PW_NTP column tiles of powers per pass;
+//  * one wave (MW = 1), for short rows: no LDS clearing or atomics, one column tile at a
+//    time through LDS;
+//  * split columns (power_mfma_cols_kernel), for more columns than one pass holds: wave w
+//    owns column tiles 4w .. 4w+3 for the whole contraction, so up to 16 column tiles take
+//    one pass, with plain LDS stores and one reassembly.
+// Loads of PW_PF K-steps are in flight together; then every thread reassembles one
+// (item, k) sum.
+constexpr int PW_MW = 4;   // waves of the split-contraction kernel
 constexpr int PW_PF = 3;   // K-steps per wave whose loads are in flight together
-constexpr int PW_NTP = 4;  // 16-column tiles per pass (4 P-limbs x 4 tiles x 4 = 64 VGPRs)
+constexpr int PW_NTP = 4;  // 16-column tiles per wave and pass (4 P-limbs x 4 tiles x 4 = 64 VGPRs)
 constexpr int PW_SHORT = 512;  // rows up to this many values take the one-wave kernel
+constexpr int PW_CTILES = 4 * PW_NTP;  // column tiles of the split-columns kernel
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// acc[c][tp] += sum over K-steps ks = ks_first, ks_first + stride, ... < ks_end of
+// A_c(ks) x B(ks, t0 + tp): A_c = 7-bit limb c of the 16 rows' values, B = limbs of a^k.
+__device__ __forceinline__ void mfma_steps(const int32_t *rp, bool iv, const uint4 *bt, int nt, int t0,
+                                           int ks_first, int ks_end, int stride, v4i (&acc)[4][PW_NTP]) {
+    for (int ks0 = ks_first; ks0 < ks_end; ks0 += PW_PF * stride) {
+        uint4 rq[PW_PF][4], bq[PW_PF][PW_NTP];
+#pragma unroll
+        for (int f = 0; f < PW_PF; ++f) {
+            const int ks = ks0 + f * stride;
+            const bool ok = ks < ks_end;
+            const uint4 *p = reinterpret_cast<const uint4 *>(rp + ks * 64);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) rq[f][i] = (ok && iv) ? p[i] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+            for (int tp = 0; tp < PW_NTP; ++tp)
+                bq[f][tp] = (ok && t0 + tp < nt) ? bt[((size_t)ks * nt + t0 + tp) * 64] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int f = 0; f < PW_PF; ++f) {
+            if (ks0 + f * stride >= ks_end) break;
+            const uint32_t v[16] = {rq[f][0].x, rq[f][0].y, rq[f][0].z, rq[f][0].w,
+                                    rq[f][1].x, rq[f][1].y, rq[f][1].z, rq[f][1].w,
+                                    rq[f][2].x, rq[f][2].y, rq[f][2].z, rq[f][2].w,
+                                    rq[f][3].x, rq[f][3].y, rq[f][3].z, rq[f][3].w};
+            v4i A[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) w |= ((v[4 * e + i] >> (7 * c)) & 0x7fu) << (8 * i);
+                    A[c][e] = (int)w;
+                }
+#pragma unroll
+            for (int tp = 0; tp < PW_NTP; ++tp) {
+                if (t0 + tp < nt) {
+                    v4i B;
+                    __builtin_memcpy(&B, &bq[f][tp], 16);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[c][tp] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[c], B, acc[c][tp], 0, 0, 0);
+                }
+            }
+        }
+    }
+}
+
+// R_k(item) += sum_u 2^(7u) sum_c 2^(7c) C_c[item][col(k, u)] over the columns of tiles
+// [tb, tb + n), whose limb-pair sums sit in ctab[c][tile - tb] ([c][tile][item*16+col]).
+// Thread tid holds (item, k) = (tid & 15, d + (tid >> 4) + (T / 16) j).
+template <int T, int NLS, int NJ, int NCT>
+__device__ __forceinline__ void reassemble(const PowerArgs &a, int d, int tb, int n, const int32_t (*ctab)[NCT][256],
+                                           mw::Int<NLS> (&R)[NJ]) {
+    const int tid = threadIdx.x, ei = tid & 15, K = a.K;
+    const int colp0 = tb * 16, colp1 = (tb + n) * 16;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int k = d + (tid >> 4) + (T / 16) * j;
+        if (k > K) break;
+        const int cs0 = a.pow.colstart[k], cs1 = a.pow.colstart[k + 1];
+        const int lo = cs0 > colp0 ? cs0 : colp0, hi = cs1 < colp1 ? cs1 : colp1;
+        for (int col = lo; col < hi; ++col) {
+            const int tp = (col >> 4) - tb, cc = col & 15;
+            uint64_t vsum = 0;  // < 2^27 * 2^22: exact
+#pragma unroll
+            for (int c = 0; c < 4; ++c) vsum += (uint64_t)(uint32_t)ctab[c][tp][ei * 16 + cc] << (7 * c);
+            if (!vsum) continue;
+            const int sh = 7 * (col - cs0);
+            add_shifted(R[j], (uint32_t)vsum, sh);
+            add_shifted(R[j], (uint32_t)(vsum >> 32), sh + 32);
+        }
+    }
+}
 
 template <int NLS, int NLR, int MW>
 __global__ void __launch_bounds__(MW * 64) power_mfma_kernel(PowerArgs a) {
-    typedef int v4i __attribute__((ext_vector_type(4)));
     constexpr int T = MW * 64;
     constexpr int NCT = MW == 1 ? 1 : PW_NTP;  // column tiles held in LDS at once
     __shared__ int32_t ctab[4][NCT][256];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     TileInfo ti;
     if (!decode_tile(a, blockIdx.x, ti)) return;  // uniform over the workgroup
-    const int K = a.K;
     const int d = ti.slot >> 1;
     const int il = lane & 15;
     const bool iv = il < ti.nitems;
     const int32_t *rp = ti.base + (iv ? (int64_t)il * ti.stride : 0) + (lane >> 4) * 16;
     const int nt = a.pow.nt;
     const uint4 *bt = a.pow.b + lane;
-
-    // reassembly work of this thread: (item, k) = (tid & 15, d + (tid >> 4) + (T / 16) j)
-    const int ei = tid & 15;
     constexpr int NJ = epi_nj<T>();
     mw::Int<NLS> R[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) mw::set_zero(R[j]);
-
-    // R_k(item) += sum_u 2^(7u) sum_c 2^(7c) C_c[item][col(k, u)] over the columns of
-    // tiles [tb, tb + n), whose limb-pair sums sit in ctab[c][tile - tb]
-    auto reassemble = [&](int tb, int n) {
-        const int colp0 = tb * 16, colp1 = (tb + n) * 16;
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int k = d + (tid >> 4) + (T / 16) * j;
-            if (k > K) break;
-            const int cs0 = a.pow.colstart[k], cs1 = a.pow.colstart[k + 1];
-            const int lo = cs0 > colp0 ? cs0 : colp0, hi = cs1 < colp1 ? cs1 : colp1;
-            for (int col = lo; col < hi; ++col) {
-                const int tp = (col >> 4) - tb, cc = col & 15;
-                uint64_t vsum = 0;  // < 2^27 * 2^22: exact
-#pragma unroll
-                for (int c = 0; c < 4; ++c) vsum += (uint64_t)(uint32_t)ctab[c][tp][ei * 16 + cc] << (7 * c);
-                if (!vsum) continue;
-                const int sh = 7 * (col - cs0);
-                add_shifted(R[j], (uint32_t)vsum, sh);
-                add_shifted(R[j], (uint32_t)(vsum >> 32), sh + 32);
-            }
-        }
-    };
 
     for (int t0 = 0; t0 < nt; t0 += PW_NTP) {
         if (MW > 1) {
@@ -196,48 +254,7 @@ __global__ void __launch_bounds__(MW * 64) power_mfma_kernel(PowerArgs a) {
         for (int c = 0; c < 4; ++c)
 #pragma unroll
             for (int tp = 0; tp < PW_NTP; ++tp) acc[c][tp] = v4i{0, 0, 0, 0};
-        for (int ks0 = ti.ks0 + wave; ks0 < ti.ks1; ks0 += PW_PF * MW) {
-            uint4 rq[PW_PF][4], bq[PW_PF][PW_NTP];
-#pragma unroll
-            for (int f = 0; f < PW_PF; ++f) {
-                const int ks = ks0 + f * MW;
-                const bool ok = ks < ti.ks1;
-                const uint4 *p = reinterpret_cast<const uint4 *>(rp + ks * 64);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) rq[f][i] = (ok && iv) ? p[i] : make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
-                for (int tp = 0; tp < PW_NTP; ++tp)
-                    bq[f][tp] = (ok && t0 + tp < nt) ? bt[((size_t)ks * nt + t0 + tp) * 64] : make_uint4(0u, 0u, 0u, 0u);
-            }
-#pragma unroll
-            for (int f = 0; f < PW_PF; ++f) {
-                if (ks0 + f * MW >= ti.ks1) break;
-                const uint32_t v[16] = {rq[f][0].x, rq[f][0].y, rq[f][0].z, rq[f][0].w,
-                                        rq[f][1].x, rq[f][1].y, rq[f][1].z, rq[f][1].w,
-                                        rq[f][2].x, rq[f][2].y, rq[f][2].z, rq[f][2].w,
-                                        rq[f][3].x, rq[f][3].y, rq[f][3].z, rq[f][3].w};
-                v4i A[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        uint32_t w = 0;
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) w |= ((v[4 * e + i] >> (7 * c)) & 0x7fu) << (8 * i);
-                        A[c][e] = (int)w;
-                    }
-#pragma unroll
-                for (int tp = 0; tp < PW_NTP; ++tp) {
-                    if (t0 + tp < nt) {
-                        v4i B;
-                        __builtin_memcpy(&B, &bq[f][tp], 16);
-#pragma unroll
-                        for (int c = 0; c < 4; ++c)
-                            acc[c][tp] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[c], B, acc[c][tp], 0, 0, 0);
-                    }
-                }
-            }
-        }
+        mfma_steps(rp, iv, bt, nt, t0, ti.ks0 + wave, ti.ks1, MW, acc);
         if (MW > 1) {
             // partial limb-pair sums of the waves -> ctab[c][tile][item][col]
 #pragma unroll
@@ -248,7 +265,7 @@ __global__ void __launch_bounds__(MW * 64) power_mfma_kernel(PowerArgs a) {
                     for (int e = 0; e < 4; ++e)
                         if (acc[c][tp][e]) atomicAdd(&ctab[c][tp][((lane >> 4) * 4 + e) * 16 + (lane & 15)], acc[c][tp][e]);
             __syncthreads();
-            reassemble(t0, PW_NTP);
+            reassemble<T, NLS, NJ, NCT>(a, d, t0, PW_NTP, ctab, R);
             __syncthreads();
         } else {
             // one wave holds the whole sums: one column tile at a time through LDS
@@ -260,11 +277,48 @@ __global__ void __launch_bounds__(MW * 64) power_mfma_kernel(PowerArgs a) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) ctab[c][0][((lane >> 4) * 4 + e) * 16 + (lane & 15)] = acc[c][tp][e];
                 __syncthreads();
-                reassemble(t0 + tp, 1);
+                reassemble<T, NLS, NJ, NCT>(a, d, t0 + tp, 1, ctab, R);
                 __syncthreads();
             }
         }
     }
+    yweight_store<T, NLS, NLR, NJ>(a, ti, blockIdx.x, d, R);
+}
+
+template <int NLS, int NLR>
+__global__ void __launch_bounds__(PW_MW * 64) power_mfma_cols_kernel(PowerArgs a) {
+    constexpr int T = PW_MW * 64;
+    __shared__ int32_t ctab[4][PW_CTILES][256];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    TileInfo ti;
+    if (!decode_tile(a, blockIdx.x, ti)) return;  // uniform over the workgroup
+    const int d = ti.slot >> 1;
+    const int il = lane & 15;
+    const bool iv = il < ti.nitems;
+    const int32_t *rp = ti.base + (iv ? (int64_t)il * ti.stride : 0) + (lane >> 4) * 16;
+    const int nt = a.pow.nt;  // <= PW_CTILES (checked at launch)
+    const uint4 *bt = a.pow.b + lane;
+    const int t0 = wave * PW_NTP;
+    v4i acc[4][PW_NTP];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int tp = 0; tp < PW_NTP; ++tp) acc[c][tp] = v4i{0, 0, 0, 0};
+    if (t0 < nt) mfma_steps(rp, iv, bt, nt, t0, ti.ks0, ti.ks1, 1, acc);
+    // every wave stores its own column tiles (tiles >= nt are never read)
+#pragma unroll
+    for (int tp = 0; tp < PW_NTP; ++tp)
+        if (t0 + tp < nt)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ctab[c][t0 + tp][((lane >> 4) * 4 + e) * 16 + (lane & 15)] = acc[c][tp][e];
+    __syncthreads();
+    constexpr int NJ = epi_nj<T>();
+    mw::Int<NLS> R[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) mw::set_zero(R[j]);
+    reassemble<T, NLS, NJ, PW_CTILES>(a, d, 0, PW_CTILES, ctab, R);
     yweight_store<T, NLS, NLR, NJ>(a, ti, blockIdx.x, d, R);
 }
 
@@ -326,11 +380,19 @@ __global__ void __launch_bounds__(PW_WAVES * 64) power_valu_kernel(PowerArgs a) 
     yweight_store<T, NLS, NLR, NJ>(a, ti, blockIdx.x, d, R);
 }
 
+// DPM_PW_NO_COLS=1 keeps multi-pass column sets on the split-contraction kernel.
+static bool power_cols_off() {
+    const char *e = std::getenv("DPM_PW_NO_COLS");
+    return e && atoi(e);
+}
+
 template <int NLS, int NLR>
 static hipError_t power_go(const PowerArgs &a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
     if (a.pow.b && a.max_len <= PW_SHORT)
         hipLaunchKernelGGL((power_mfma_kernel<NLS, NLR, 1>), dim3(a.ntiles), dim3(64), 0, st, a);
+    else if (a.pow.b && a.pow.nt > PW_NTP && a.pow.nt <= PW_CTILES && !power_cols_off())
+        hipLaunchKernelGGL((power_mfma_cols_kernel<NLS, NLR>), dim3(a.ntiles), dim3(PW_MW * 64), 0, st, a);
     else if (a.pow.b)
         hipLaunchKernelGGL((power_mfma_kernel<NLS, NLR, PW_MW>), dim3(a.ntiles), dim3(PW_MW * 64), 0, st, a);
     else hipLaunchKernelGGL((power_valu_kernel<NLS, NLR>), dim3(a.ntiles), dim3(PW_WAVES * 64), 0, st, a);
