@@ -134,7 +134,10 @@ size_t dpm_batched_workspace_bytes(const dpm_roi *rois, int n_rois, int max_orde
 /* All ROIs in one launch sequence on `stream`: a prep kernel (per-ROI geometry and
  * work items), the projection of every (ROI, y) slice, the power-sum tiles of every
  * ROI, and one recombination per (ROI, moment).  Orders <= 6 (else DPM_ENOTSUP); ROI
- * dims <= 4096 (else DPM_ERANGE).  out_device->exact / ->fp64 hold n_rois consecutive
+ * dims <= 4096, and every ROI's image rows over its whole z range must fit the LDS of
+ * one workgroup (160 KB; e.g. a 1 x 1 x 4096 column at order 6 does not), else
+ * DPM_ERANGE -- dpm_batched_workspace_bytes then returns 0; such a volume goes through
+ * dpm_moments_async, which splits z.  out_device->exact / ->fp64 hold n_rois consecutive
  * result blocks (block i at i * dpm_num_moments(...)); workspace must hold
  * dpm_batched_workspace_bytes() bytes (else DPM_ENOMEM).
  *

@@ -83,6 +83,7 @@ int elem_of(int dt) { return dt == DPM_U8 ? 1 : dt == DPM_U16 ? 2 : 0; }
 struct Req {
     dpm_request r;
     double t_arr;
+    bool batchable = false;  // the batched path can plan this volume on its own
     size_t bytes() const { return (size_t)(r.dims[0] * r.dims[1] * r.dims[2]) * (size_t)elem_of(r.dtype); }
     int64_t voxels() const { return r.dims[0] * r.dims[1] * r.dims[2]; }
 };
@@ -133,10 +134,7 @@ struct dpm_server {
         const size_t s = (size_t)dpm::n_moments(4) * 16 + (size_t)dpm::n_moments(dpm::KMAX) * 8;
         return al(std::max(b, s));
     }
-    bool small(const Req &q) const {
-        return q.r.max_order <= 6 && q.voxels() <= cfg.batch_voxels && q.r.dims[0] <= 4096 && q.r.dims[1] <= 4096 &&
-               q.r.dims[2] <= 4096;
-    }
+    bool small(const Req &q) const { return q.batchable && q.voxels() <= cfg.batch_voxels; }
 
     void release_blocks(Job &j) {
         for (auto &b : j.blocks) (b.host ? parena : darena)->release(b.off, b.n);
@@ -399,6 +397,16 @@ int dpm_server_submit(dpm_server *s, const dpm_request *req) {
         req->dims[0] <= 0 || req->dims[1] <= 0 || req->dims[2] <= 0)
         return DPM_EINVAL;
     Req q{*req, req->t_arrival_ms > 0 ? req->t_arrival_ms : now_ms_impl()};
+    if (req->max_order <= 6 && req->dims[0] <= 4096 && req->dims[1] <= 4096 && req->dims[2] <= 4096) {
+        // batchable if the batched planner accepts it alone (then also in any batch:
+        // a batch plan takes the maximum of its ROIs' widths and LDS)
+        dpm_roi roi{};
+        roi.dims[0] = req->dims[0];
+        roi.dims[1] = req->dims[1];
+        roi.dims[2] = req->dims[2];
+        roi.dtype = req->dtype;
+        q.batchable = dpm_batched_workspace_bytes(&roi, 1, req->max_order) > 0;
+    }
     // refuse what can never fit: its own blocks exceed the whole arena
     const size_t ws = dpm_workspace_bytes(req->dims, (dpm_dtype)req->dtype, req->max_order);
     if (!ws) return DPM_ERANGE;

@@ -75,6 +75,11 @@ MOMENT_CASES = [
     ((16, 8, 64), np.uint8, 1),
     ((32, 3, 512), np.uint16, 6),
     ((96, 2, 1024), np.uint16, 5),
+    # size limits of the matrix-core power sums: row values reach 2^28 (L = 4100 at
+    # uint16), coordinates a reach 8192 (L = 4096): both take the VALU power sums
+    ((16, 2, 4100), np.uint16, 6),
+    ((16, 2, 4096), np.uint16, 6),
+    ((4100, 3, 2), np.uint16, 5),     # N = 4100: many z-splits per slice
 ]
 
 
@@ -307,3 +312,55 @@ def test_batched_graph_replays(dpm, monkeypatch):
     assert dpm.batched_graph_count() == 1
     dpm.release()
     assert dpm.batched_graph_count() == 0
+
+
+def test_large_planes_order3(dpm):
+    """A 3000 x 2 x 3000 uint16 volume (wide rows and many z rows at once)."""
+    say("3000x2x3000 u16 K=3")
+    V = synth.uniform_volume((3000, 2, 3000), np.uint16, seed=9)
+    res = dpm.moments(to_dev(V), 3)
+    assert_moments_equal(res, onative.moments_hoisted(V, 3), 3, "3000x2x3000")
+
+
+def test_batched_extreme_roi_shapes(dpm):
+    """Batched ROIs at the batched path's size limit (4096 along one axis), single voxels,
+    and both dtypes in one batch: each equals its single call and the oracle."""
+    import torch
+    say("batched extreme shapes")
+    shapes = [((1, 1, 1), np.uint8), ((3, 2, 4096), np.uint16), ((2048, 1, 1), np.uint8),
+              ((1, 4096, 1), np.uint16), ((2, 3, 4096), np.uint8), ((5, 7, 9), np.uint16),
+              ((64, 1, 64), np.uint8)]
+    rois = [synth.uniform_volume(sh, dt, seed=i) for i, (sh, dt) in enumerate(shapes)]
+    K = 6
+    packed, desc = dpm.pack_rois(rois, "cuda:0")
+    n, nm, nm4 = len(rois), dpm.num_moments(K), dpm.num_moments(4)
+    ex = torch.zeros((n * nm4, 2), dtype=torch.int64, device="cuda:0")
+    fp = torch.zeros(n * nm, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(dpm.batched_workspace_bytes(desc, K), dtype=torch.uint8, device="cuda:0")
+    dpm.moments_batched(packed, desc, K, ex, fp, ws)
+    torch.cuda.synchronize()
+    exact = dpm._exact_from_tensor(ex)
+    fpn = fp.cpu().numpy()
+    for i, V in enumerate(rois):
+        got = dpm.Moments(K, exact[i * nm4:(i + 1) * nm4], fpn[i * nm:(i + 1) * nm])
+        assert_moments_equal(got, oracle.moments_exact(V, K), K, f"roi {i} {V.shape}")
+        single = dpm.moments(to_dev(V), K)
+        assert single.exact == got.exact
+
+
+def test_batched_refuses_rows_beyond_lds(dpm):
+    """A 4096-deep column at order 6 needs more LDS for its full-z image rows than one
+    workgroup has: the batched planner refuses it (workspace size 0, DPM_ERANGE), and the
+    single-volume path, which splits z, computes it."""
+    import ctypes
+    import torch
+    from paper_2012_08099_amd import _lib
+    V = synth.uniform_volume((4096, 1, 1), np.uint8, seed=4)
+    packed, desc = dpm.pack_rois([V], "cuda:0")
+    assert dpm.batched_workspace_bytes(desc, 6) == 0
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda:0")
+    out = _lib.Out(None, torch.zeros(84, dtype=torch.float64, device="cuda:0").data_ptr())
+    rc = dpm.lib().dpm_moments_batched(ctypes.c_void_p(packed.data_ptr()), desc, 1, 6, ctypes.byref(out),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
+    assert rc == -2
+    assert_moments_equal(dpm.moments(to_dev(V), 6), oracle.moments_exact(V, 6), 6, "4096 column")

@@ -134,3 +134,22 @@ def test_server_same_volume_alone_and_in_a_mix(dpm):
     assert mine["batched"]
     assert mine["moments"].exact == alone.exact
     assert np.array_equal(mine["moments"].fp64.view(np.uint64), alone.fp64.view(np.uint64))
+
+
+def test_server_serves_unbatchable_small_request_alone(dpm):
+    """A request that is small in voxels but whose full-z image rows exceed the batched
+    path's LDS (a 4096-deep column at order 6) is served by the single-volume path."""
+    say("server unbatchable")
+    V = synth.uniform_volume((4096, 1, 1), np.uint8, seed=1)
+    W = synth.uniform_volume((20, 20, 20), np.uint8, seed=2)
+    srv = dpm.Server(hbm_budget=1 << 28, n_streams=1, batch_voxels=1 << 20)
+    try:
+        tv = srv.submit(to_dev(V), 6)
+        tw = srv.submit(to_dev(W), 6)
+        done = {c["tag"]: c for c in drain(srv, 2)}
+    finally:
+        srv.close()
+    assert done[tv]["status"] == 0 and not done[tv]["batched"]
+    assert done[tw]["status"] == 0 and done[tw]["batched"]
+    assert_moments_equal(done[tv]["moments"], oracle.moments_exact(V, 6), 6, "column")
+    assert_moments_equal(done[tw]["moments"], oracle.moments_exact(W, 6), 6, "cube")
