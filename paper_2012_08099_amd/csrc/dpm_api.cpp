@@ -193,6 +193,7 @@ struct Plan {
     bool mfma = false;   // power sums on the matrix cores
     int pow_passes = 0;  // column-tile passes of the matrix-core power kernel
     dpm_tuning tune{};   // override of this shape (dpm_tune_set), zero if none
+    bool one_launch = false;  // orders 7-16: all direction groups in one projection launch
     int amax = 0;        // coordinate magnitudes covered by the power table
     RowLayout rl{};
     int nslots_used = 0;
@@ -321,6 +322,7 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
     if (const char *e = std::getenv("DPM_FORCE_GENERIC")) {
         if (atoi(e)) p.fast = false;
     }
+
     // chained-window projection: opt-in (it is exact, but measured slower than the
     // windowed kernel on the 512^3 workload)
     p.chain = false;
@@ -351,6 +353,10 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
         }
         p.lds[g] = best;
         if (best > 160 * 1024) return DPM_ERANGE;
+    }
+    p.one_launch = p.fast && p.ngroups > 1;
+    if (const char *e = std::getenv("DPM_GROUP_LAUNCHES")) {
+        if (atoi(e)) p.one_launch = false;
     }
     int64_t off = 0, amax = 64;
     for (int sl = 0; sl < NSLOT; ++sl) {
@@ -441,7 +447,27 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
         if (prc) return prc;
     }
     if (moments) prof_mark(0, st);
-    for (int g = 0; g < p.ngroups; ++g) {
+    if (p.one_launch && !images) {
+        // orders 7-16: every direction group in one launch, sibling workgroups per item
+        SliceArgs a{};
+        a.vol = static_cast<const uint8_t *>(vol);
+        a.L = p.L;
+        a.M = p.M;
+        a.N = p.N;
+        a.pitch_y = p.L;
+        a.pitch_z = p.L * p.M;
+        a.zsplits = p.zsplits;
+        a.zrows = p.zrows;
+        a.R = p.R;
+        a.CT = p.CT;
+        a.rows = rows;
+        a.rl = p.rl;
+        size_t lds = 0;
+        for (int g = 0; g < p.ngroups; ++g) lds = std::max(lds, p.lds[g]);
+        hipError_t e = launch_slice_groups(p.elem, p.nd, a, p.items, lds, st);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    for (int g = 0; g < p.ngroups && !(p.one_launch && !images); ++g) {
         SliceArgs a{};
         a.vol = static_cast<const uint8_t *>(vol);
         a.L = p.L;

@@ -108,6 +108,9 @@ hipError_t launch_slice(int elem, bool fast, bool chain, int g, int nd, const Sl
 // One workgroup per ROI: its geometry, its work items (launch order item_pos + y) and
 // the labels of its power-sum tiles.
 hipError_t launch_batched_prep(int nd, const BatchSliceArgs &a, int nrois, hipStream_t st);
+// Orders 7-16, whole-row loads, moments only: all direction groups in one launch
+// (nd = K + 1 directions in total; lds = the largest group's LDS).
+hipError_t launch_slice_groups(int elem, int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st);
 hipError_t launch_slice_batched(int elem, int g, int nd, const BatchSliceArgs &a, int items, size_t lds,
                                 hipStream_t st);
 

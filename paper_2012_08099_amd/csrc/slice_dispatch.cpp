@@ -13,6 +13,12 @@ hipError_t launch_slice_g12_u16(int g, bool fast, int nd, const SliceArgs &a, in
                                 hipStream_t st);
 hipError_t launch_slice_g12_u8(int g, bool fast, int nd, const SliceArgs &a, int items, size_t lds,
                                hipStream_t st);
+hipError_t launch_slice_groups_u16(int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st);
+hipError_t launch_slice_groups_u8(int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st);
+
+hipError_t launch_slice_groups(int elem, int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st) {
+    return elem == 2 ? launch_slice_groups_u16(nd, a, items, lds, st) : launch_slice_groups_u8(nd, a, items, lds, st);
+}
 
 hipError_t launch_slice(int elem, bool fast, bool chain, int g, int nd, const SliceArgs &a, int items, size_t lds,
                         hipStream_t st) {

@@ -737,6 +737,73 @@ slice_kernel(SliceArgs a) {
                                  a.rl.slot_len, a.images, a.img_off, a.img_w, lds, ig);
 }
 
+// Orders 7-16 in one launch: the direction groups of one work item run as sibling
+// workgroups dispatched back to back onto the same XCD (the dispatcher hands workgroups
+// to the 8 XCDs round-robin in index order), so the item's rows come from HBM about once
+// and to the siblings from that XCD's L2 or the MALL.  Block b: XCD x = b % 8, local
+// index l = b / 8; item = (l / NG) * 8 + x, group = l % NG.  Moments only (no images),
+// whole-row loads only.
+constexpr int NXCD = 8;
+
+template <typename VT, int ND1, int ND2>
+__global__ void __launch_bounds__(slice_waves((int)sizeof(VT)) * 64)
+slice_groups_kernel(SliceArgs a, int items) {
+    extern __shared__ uint32_t lds[];
+    __shared__ ItemGeom ig;
+    constexpr int NG = ND2 > 0 ? 3 : 2;
+    constexpr int NW = slice_waves((int)sizeof(VT));
+    const int b = blockIdx.x, x = b % NXCD, l = b / NXCD;
+    const int64_t item = (int64_t)(l / NG) * NXCD + x;
+    const int g = l % NG;
+    if (item >= items) return;  // uniform over the workgroup
+    const int64_t y = item / a.zsplits;
+    const int64_t zs = (item % a.zsplits) * a.zrows;
+    const int64_t ze = zs + a.zrows < a.N ? zs + a.zrows : a.N;
+    const VT *vol = reinterpret_cast<const VT *>(a.vol);
+    int32_t *rows = a.rows + item * a.rl.row_stride;
+    if (g == 0)
+        slice_item<VT, 0, 7, true, false, NW>(vol, a.L, a.N, a.pitch_y, a.pitch_z, y, zs, ze, a.R, a.CT, rows,
+                                              a.rl.slot_off, a.rl.slot_len, nullptr, nullptr, nullptr, lds, ig);
+    else if (g == 1)
+        slice_item<VT, 7, ND1, true, false, NW>(vol, a.L, a.N, a.pitch_y, a.pitch_z, y, zs, ze, a.R, a.CT, rows,
+                                                a.rl.slot_off, a.rl.slot_len, nullptr, nullptr, nullptr, lds, ig);
+    else if constexpr (ND2 > 0)
+        slice_item<VT, 12, ND2, true, false, NW>(vol, a.L, a.N, a.pitch_y, a.pitch_z, y, zs, ze, a.R, a.CT, rows,
+                                                 a.rl.slot_off, a.rl.slot_len, nullptr, nullptr, nullptr, lds, ig);
+}
+
+template <typename VT, int ND1, int ND2>
+hipError_t launch_groups_one(const SliceArgs &a, int items, size_t lds, hipStream_t st) {
+    auto k = slice_groups_kernel<VT, ND1, ND2>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    constexpr int NG = ND2 > 0 ? 3 : 2;
+    const int64_t blocks = (int64_t)((items + NXCD - 1) / NXCD) * NXCD * NG;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(slice_waves((int)sizeof(VT)) * 64), lds, st, a, items);
+    return hipGetLastError();
+}
+
+// nd = K + 1 in 8 .. 17
+template <typename VT>
+hipError_t launch_groups_nd(int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st) {
+    switch (nd) {
+        case 8: return launch_groups_one<VT, 1, 0>(a, items, lds, st);
+        case 9: return launch_groups_one<VT, 2, 0>(a, items, lds, st);
+        case 10: return launch_groups_one<VT, 3, 0>(a, items, lds, st);
+        case 11: return launch_groups_one<VT, 4, 0>(a, items, lds, st);
+        case 12: return launch_groups_one<VT, 5, 0>(a, items, lds, st);
+        case 13: return launch_groups_one<VT, 5, 1>(a, items, lds, st);
+        case 14: return launch_groups_one<VT, 5, 2>(a, items, lds, st);
+        case 15: return launch_groups_one<VT, 5, 3>(a, items, lds, st);
+        case 16: return launch_groups_one<VT, 5, 4>(a, items, lds, st);
+        case 17: return launch_groups_one<VT, 5, 5>(a, items, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // Batched items are small slices of small volumes: one wave per item, so that many
 // items run side by side on a CU.
 constexpr int BATCH_WAVES = 1;

@@ -80,6 +80,11 @@ MOMENT_CASES = [
     ((16, 2, 4100), np.uint16, 6),
     ((16, 2, 4096), np.uint16, 6),
     ((4100, 3, 2), np.uint16, 5),     # N = 4100: many z-splits per slice
+    # orders 7-16 on whole-row loads: all direction groups in one launch
+    ((48, 9, 64), np.uint8, 7),
+    ((32, 5, 128), np.uint16, 11),
+    ((64, 3, 256), np.uint16, 13),
+    ((48, 7, 512), np.uint8, 16),
 ]
 
 
@@ -97,6 +102,8 @@ PATH_OVERRIDES = [
     ({"DPM_ZSPLITS": "3"}, (48, 10, 64), np.uint16, 7),     # z-split work items
     ({"DPM_ZSPLITS": "4", "DPM_NO_MFMA": "1"}, (70, 5, 64), np.uint8, 5),
     ({"DPM_FORCE_GENERIC": "1"}, (32, 8, 128), np.uint16, 6),
+    ({"DPM_GROUP_LAUNCHES": "1"}, (32, 8, 128), np.uint16, 16),  # one launch per direction group
+    ({"DPM_GROUP_LAUNCHES": "1"}, (48, 5, 64), np.uint8, 9),
     # chained-window projection (opt-in): rows of whole 64-lane tiles, 32-row units
     ({"DPM_CHAIN": "1"}, (32, 3, 512), np.uint16, 6),
     ({"DPM_CHAIN": "1"}, (96, 2, 1024), np.uint16, 5),
