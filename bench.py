@@ -37,7 +37,10 @@ WORKLOADS = {
     "ct512_k16": ((512, 512, 512), "u16", 16, "ct"),
     "mri256_k6": ((256, 256, 256), "u16", 6, "mri"),
     "u8_64_k3": ((64, 64, 64), "u8", 3, "uniform"),
+    # 128 MB of 1-byte voxels at order 4: the size of one row of the paper's Table 1
+    "u8_512_k4": ((512, 512, 512), "u8", 4, "uniform"),
 }
+GEN_DESC = {"ct": "CT-like phantom", "mri": "MRI-like phantom", "uniform": "uniform random voxels"}
 
 
 def log(*a):
@@ -414,7 +417,7 @@ def main(argv=None):
         "vs_baseline": None,
         "dtype": "u16" if elem == 2 else "u8",
         "data": "synthetic",
-        "config": {"workload": f"{a.workload}: {L}x{M}x{N} {dt} CT-like phantom, max_order {K} "
+        "config": {"workload": f"{a.workload}: {L}x{M}x{N} {dt} {GEN_DESC[gen]}, max_order {K} "
                                f"({nm} moments; orders<=4 exact int128, all FP64)", "volumes_rotated": a.nvol,
                    "streams": depth},
         "hbm_gbs_algorithmic": voxels * elem / (ms_step / 1e3) / 1e9,
