@@ -173,7 +173,11 @@ def serve_main(a):
             finally:
                 srv.close()
             bad = [c for c in done if c["status"] != 0]
-            assert not bad, f"{len(bad)} requests failed"
+            if bad:
+                import collections
+                kinds = collections.Counter((c["status"], c["batched"]) for c in bad)
+                raise RuntimeError(f"{len(bad)} of {len(done)} requests failed; (status, batched): {dict(kinds)}; "
+                                   f"last device error {dpm.lib().dpm_last_device_error()}")
             lat = np.array([c["t_done_ms"] - c["t_arrival_ms"] for c in done])
             t_first = min(c["t_arrival_ms"] for c in done)
             t_last = max(c["t_done_ms"] for c in done)

@@ -146,8 +146,10 @@ size_t dpm_batched_workspace_bytes(const dpm_roi *rois, int n_rois, int max_orde
  * launch sequence is captured into a hipGraph on the second sighting and replayed from
  * then on, with no host planning and no descriptor upload; the contents of `packed` may
  * change between calls.  Up to 16 graphs are cached, least recently used evicted; they
- * are freed by dpm_release.  Graphs are not used while stage timing is enabled or when
- * the environment sets DPM_NO_GRAPH=1.  Not safe against concurrent calls that share a
+ * are freed by dpm_release.  Graphs are not used while stage timing is enabled, when
+ * the environment sets DPM_NO_GRAPH=1, or for the served loop's batches (they rarely
+ * repeat, and a capture allocates synchronously).  A graph whose launch fails is dropped
+ * and the call runs without it.  Not safe against concurrent calls that share a
  * workspace. */
 int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int max_order,
                         const dpm_out *out_device, void *workspace, size_t ws_bytes,

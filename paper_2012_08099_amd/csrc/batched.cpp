@@ -23,6 +23,8 @@ int batched_numsum_bits(int k);
 void batched_set_error(int e);
 void batched_prof_mark(int idx, hipStream_t st);
 bool batched_profiling();
+int batched_run(const void *packed, const dpm_roi *rois, int n_rois, int max_order, const dpm_out *out_device,
+                void *workspace, size_t ws_bytes, void *stream, bool allow_graphs);
 int batched_powtab(int amax, int K, PowTab &out);
 bool batched_pow_columns(int amax, int K, int32_t colstart[KMAX + 2]);
 }  // namespace dpm
@@ -340,13 +342,16 @@ bool build_and_launch_graph(const GraphKey &key, const BPlan &p, const PowTab &p
     g.last_use = ++g_graph_tick;
     e = hipGraphLaunch(g.exec, st);
     if (e == hipSuccess) e = hipEventRecord(g.done, st);
-    g_graphs.push_back(g);
     if (e != hipSuccess) {
+        // not cached; clear the error so that the caller's eager launch starts clean (a
+        // real device fault shows again there)
         batched_set_error((int)e);
-        // the graph stays cached; this call's launch failed and is reported by the
-        // caller's next device error check
+        (void)hipGetLastError();
+        destroy_entry(g);
+        return false;
     }
-    return e == hipSuccess;
+    g_graphs.push_back(g);
+    return true;
 }
 
 }  // namespace
@@ -382,12 +387,28 @@ size_t dpm_batched_workspace_bytes(const dpm_roi *rois, int n_rois, int max_orde
 
 int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int max_order,
                         const dpm_out *out_device, void *workspace, size_t ws_bytes, void *stream) {
+    return dpm::batched_run(packed, rois, n_rois, max_order, out_device, workspace, ws_bytes, stream, true);
+}
+
+int dpm_batched_graph_count(void) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    return (int)g_graphs.size();
+}
+
+}  // extern "C"
+
+namespace dpm {
+// The batched call; `graphs`: whether a repeated call may be captured and replayed (the
+// served loop passes false: its batches rarely repeat, and a capture's synchronous
+// allocation would stall its worker).
+int batched_run(const void *packed, const dpm_roi *rois, int n_rois, int max_order, const dpm_out *out_device,
+                void *workspace, size_t ws_bytes, void *stream, bool allow_graphs) {
     if (!packed || !out_device || !workspace) return DPM_EINVAL;
     int rc = batched_ensure_tables();
     if (rc) return rc;
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = hipSuccess;
-    const bool graphs = graphs_enabled() && rois && n_rois > 0 && max_order >= 0 && max_order <= 6;
+    const bool graphs = allow_graphs && graphs_enabled() && rois && n_rois > 0 && max_order >= 0 && max_order <= 6;
     GraphKey key;
     bool repeat = false;
     if (graphs) {
@@ -406,19 +427,21 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
                         reinterpret_cast<const uint8_t *>(rois) + sizeof(dpm_roi) * (size_t)n_rois);
         key.hash = key_hash(key);
         std::lock_guard<std::mutex> lk(g_graph_mu);
-        for (auto &g : g_graphs)
-            if (g.key == key) {
+        for (auto it = g_graphs.begin(); it != g_graphs.end(); ++it)
+            if (it->key == key) {
                 // a repeated call: replay its graph (no planning, no descriptor upload)
-                g.last_use = ++g_graph_tick;
-                e = hipGraphLaunch(g.exec, st);
-                if (e == hipSuccess) e = hipEventRecord(g.done, st);
-                if (e != hipSuccess) {
-                    batched_set_error((int)e);
-                    return DPM_EDEVICE;
-                }
-                return DPM_OK;
+                it->last_use = ++g_graph_tick;
+                e = hipGraphLaunch(it->exec, st);
+                if (e == hipSuccess) e = hipEventRecord(it->done, st);
+                if (e == hipSuccess) return DPM_OK;
+                // drop the graph and run the call eagerly below
+                batched_set_error((int)e);
+                (void)hipGetLastError();
+                destroy_entry(*it);
+                g_graphs.erase(it);
+                break;
             }
-        repeat = seen_before(key.hash);
+        if (e == hipSuccess) repeat = seen_before(key.hash);
     }
     BPlan p;
     if ((rc = bplan(rois, n_rois, max_order, p))) return rc;
@@ -447,10 +470,4 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
     }
     return DPM_OK;
 }
-
-int dpm_batched_graph_count(void) {
-    std::lock_guard<std::mutex> lk(g_graph_mu);
-    return (int)g_graphs.size();
-}
-
-}  // extern "C"
+}  // namespace dpm

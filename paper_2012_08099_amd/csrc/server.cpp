@@ -24,6 +24,11 @@
 #include "../../include/dpm.h"
 #include "dpm_common.h"
 
+namespace dpm {
+int batched_run(const void *packed, const dpm_roi *rois, int n_rois, int max_order, const dpm_out *out_device,
+                void *workspace, size_t ws_bytes, void *stream, bool allow_graphs);  // batched.cpp
+}  // namespace dpm
+
 namespace {
 
 double now_ms_impl() {
@@ -203,7 +208,7 @@ int dpm_server::launch(Job &j) {
         const Block &ob = j.blocks[bi++];
         dpm_out out{reinterpret_cast<dpm_i128 *>(dev + ob.off),
                     reinterpret_cast<double *>(dev + ob.off + (size_t)n * nm4 * 16)};
-        int rc = dpm_moments_batched(packed, rois.data(), n, j.K, &out, dev + wb.off, wb.n, s);
+        int rc = dpm::batched_run(packed, rois.data(), n, j.K, &out, dev + wb.off, wb.n, s, false);
         if (rc) return rc;
         e = hipMemcpyAsync(pin + j.res_off, dev + ob.off, (size_t)n * (nm4 * 16 + nm * 8), hipMemcpyDeviceToHost, s);
     } else {
