@@ -179,13 +179,24 @@ def serve_main(a):
                 raise RuntimeError(f"{len(bad)} of {len(done)} requests failed; (status, batched): {dict(kinds)}; "
                                    f"last device error {dpm.lib().dpm_last_device_error()}")
             lat = np.array([c["t_done_ms"] - c["t_arrival_ms"] for c in done])
+            wait = np.array([c["t_start_ms"] - c["t_arrival_ms"] for c in done])
+            bat = np.array([bool(c["batched"]) for c in done])
             t_first = min(c["t_arrival_ms"] for c in done)
             t_last = max(c["t_done_ms"] for c in done)
             span_s = (t_last - t_first) / 1e3
+            tail = lat >= np.percentile(lat, 99)
+            t_tail = np.array([c["t_arrival_ms"] for c in done])[tail] - t_first
             return {"offered_per_s": rate_hz, "served_per_s": len(done) / span_s,
                     "voxels_per_s": nvox / span_s, "p50_ms": float(np.percentile(lat, 50)),
                     "p99_ms": float(np.percentile(lat, 99)), "batched_jobs": st["batched_jobs"],
-                    "single_jobs": st["single_jobs"], "arena_peak_gib": st["arena_peak_used"] / 2 ** 30}
+                    "single_jobs": st["single_jobs"], "arena_peak_gib": st["arena_peak_used"] / 2 ** 30,
+                    # where the slowest 1% spend their time, and when they arrived
+                    "tail": {"n": int(tail.sum()), "wait_ms_mean": float(wait[tail].mean()),
+                             "run_ms_mean": float((lat - wait)[tail].mean()),
+                             "batched_frac": float(bat[tail].mean()),
+                             "arrival_s_min": float(t_tail.min() / 1e3), "arrival_s_max": float(t_tail.max() / 1e3)},
+                    "p99_ms_batched": float(np.percentile(lat[bat], 99)) if bat.any() else None,
+                    "p99_ms_single": float(np.percentile(lat[~bat], 99)) if (~bat).any() else None}
 
         cap = run(0.0)
         log(mode, "capacity", cap)

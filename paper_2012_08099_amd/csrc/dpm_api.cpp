@@ -103,6 +103,9 @@ bool pow_columns(int amax, int K, int32_t colstart[KMAX + 2]) {
 }
 
 int get_powtab(int amax, int K, PowTab &out) {
+    // one table per 512 values of a: a table serves every shorter row, so a stream of
+    // mixed shapes builds few tables (each build allocates and copies synchronously)
+    amax = (amax + 511) / 512 * 512;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e);

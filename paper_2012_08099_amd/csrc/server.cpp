@@ -380,6 +380,10 @@ int dpm_server_create(const dpm_server_config *cfg, dpm_server **out) {
         ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;  // default priority
         if (ok) s->streams.push_back(st);
     }
+    // warm every stream before serving: its first dispatch binds it to a hardware queue,
+    // which would otherwise delay the first requests by milliseconds
+    for (size_t i = 0; ok && i < s->streams.size(); ++i)
+        ok = hipMemsetAsync(s->dev, 0, 256, s->streams[i]) == hipSuccess && hipStreamSynchronize(s->streams[i]) == hipSuccess;
     (void)hipSetDevice(cur);
     if (!ok) {
         for (auto st : s->streams) (void)hipStreamDestroy(st);
