@@ -163,6 +163,13 @@ struct GroupTraits {
 };
 
 // ------------------------------------------------------------ step 1: projection
+// Units (T rows of a lane's voxels) whose loads are in flight per wave.  The workgroup
+// count, not the register file, bounds the occupancy of the projection, so the buffers
+// can be deep.
+#ifndef SLICE_UNITS_IN_FLIGHT
+#define SLICE_UNITS_IN_FLIGHT 2
+#endif
+
 template <typename VT, int D0, int ND, bool FAST, int NW>
 __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pitch_z, int64_t zs,
                              int64_t ze, int R, int CT, uint32_t *lds, const ItemGeom &ig) {
@@ -312,20 +319,31 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
         }
     };
 
-    // two units in flight: the loads of unit u+1 are issued before unit u is summed
-    Vec bufA[T], bufB[T];
+    // NB units in flight: the loads of unit u + NB - 1 are issued before unit u is summed
+    // (buffer u % NB; the position of unit u + 1 tells whether u ends its column tile)
+    constexpr int NB = SLICE_UNITS_IN_FLIGHT;
+    Vec buf[NB][T];
+    Pos pos[NB];
     if (u_begin >= u_end) return;
     const int32_t n = (int32_t)(u_end - u_begin);
-    Pos pa = pos_of(u_begin), pb;
-    load_unit(bufA, pa);
-    for (int32_t k = 0; k < n; k += 2) {
-        pb = next_pos(pa);
-        if (k + 1 < n) load_unit(bufB, pb);
-        process_unit(bufA, pa, k + 1 >= n || pb.ct != pa.ct);
-        if (k + 1 >= n) break;
-        pa = next_pos(pb);
-        if (k + 2 < n) load_unit(bufA, pa);
-        process_unit(bufB, pb, k + 2 >= n || pa.ct != pb.ct);
+    pos[0] = pos_of(u_begin);
+    load_unit(buf[0], pos[0]);
+    StaticFor<1, NB - 1>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        pos[i] = next_pos(pos[i - 1]);
+        if (i < n) load_unit(buf[i], pos[i]);
+    });
+    for (int32_t k = 0; k < n; k += NB) {
+        StaticFor<0, NB>::run([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr int lj = (j + NB - 1) % NB, pj = (j + NB - 2) % NB, nj = (j + 1) % NB;
+            const int32_t u = k + j;
+            if (u < n) {
+                pos[lj] = next_pos(pos[pj]);
+                if (u + NB - 1 < n) load_unit(buf[lj], pos[lj]);
+                process_unit(buf[j], pos[j], u + 1 >= n || pos[nj].ct != pos[j].ct);
+            }
+        });
     }
 }
 
