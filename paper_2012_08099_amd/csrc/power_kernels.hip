@@ -150,51 +150,72 @@ constexpr int PW_CTILES = 4 * PW_NTP;  // column tiles of the split-columns kern
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
+// Loads of PF K-steps: the 16 rows' values (A) and the limbs of a^k (B) of column tiles
+// t0 .. t0 + PW_NTP - 1; zero past ks_end or past the rows.
+template <int PF>
+struct StepBuf {
+    uint4 rq[PF][4], bq[PF][PW_NTP];
+};
+
+template <int PF>
+__device__ __forceinline__ void load_steps(StepBuf<PF> &b, const int32_t *rp, bool iv, const uint4 *bt, int nt,
+                                           int t0, int ks0, int ks_end, int stride) {
+#pragma unroll
+    for (int f = 0; f < PF; ++f) {
+        const int ks = ks0 + f * stride;
+        const bool ok = ks < ks_end;
+        const uint4 *p = reinterpret_cast<const uint4 *>(rp + ks * 64);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b.rq[f][i] = (ok && iv) ? p[i] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int tp = 0; tp < PW_NTP; ++tp)
+            b.bq[f][tp] = (ok && t0 + tp < nt) ? bt[((size_t)ks * nt + t0 + tp) * 64] : make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+// acc[c][tp] += A_c(ks) x B(ks, t0 + tp) for the PF K-steps of b: A_c = 7-bit limb c of
+// the rows' values.
+template <int PF>
+__device__ __forceinline__ void mma_steps(const StepBuf<PF> &b, int nt, int t0, int ks0, int ks_end, int stride,
+                                          v4i (&acc)[4][PW_NTP]) {
+#pragma unroll
+    for (int f = 0; f < PF; ++f) {
+        if (ks0 + f * stride >= ks_end) break;
+        const uint32_t v[16] = {b.rq[f][0].x, b.rq[f][0].y, b.rq[f][0].z, b.rq[f][0].w,
+                                b.rq[f][1].x, b.rq[f][1].y, b.rq[f][1].z, b.rq[f][1].w,
+                                b.rq[f][2].x, b.rq[f][2].y, b.rq[f][2].z, b.rq[f][2].w,
+                                b.rq[f][3].x, b.rq[f][3].y, b.rq[f][3].z, b.rq[f][3].w};
+        v4i A[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint32_t w = 0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) w |= ((v[4 * e + i] >> (7 * c)) & 0x7fu) << (8 * i);
+                A[c][e] = (int)w;
+            }
+#pragma unroll
+        for (int tp = 0; tp < PW_NTP; ++tp) {
+            if (t0 + tp < nt) {
+                v4i B;
+                __builtin_memcpy(&B, &b.bq[f][tp], 16);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[c][tp] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[c], B, acc[c][tp], 0, 0, 0);
+            }
+        }
+    }
+}
+
 // acc[c][tp] += sum over K-steps ks = ks_first, ks_first + stride, ... < ks_end of
-// A_c(ks) x B(ks, t0 + tp): A_c = 7-bit limb c of the 16 rows' values, B = limbs of a^k.
+// A_c(ks) x B(ks, t0 + tp), PW_PF K-steps per batch of loads.
 __device__ __forceinline__ void mfma_steps(const int32_t *rp, bool iv, const uint4 *bt, int nt, int t0,
                                            int ks_first, int ks_end, int stride, v4i (&acc)[4][PW_NTP]) {
     for (int ks0 = ks_first; ks0 < ks_end; ks0 += PW_PF * stride) {
-        uint4 rq[PW_PF][4], bq[PW_PF][PW_NTP];
-#pragma unroll
-        for (int f = 0; f < PW_PF; ++f) {
-            const int ks = ks0 + f * stride;
-            const bool ok = ks < ks_end;
-            const uint4 *p = reinterpret_cast<const uint4 *>(rp + ks * 64);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) rq[f][i] = (ok && iv) ? p[i] : make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
-            for (int tp = 0; tp < PW_NTP; ++tp)
-                bq[f][tp] = (ok && t0 + tp < nt) ? bt[((size_t)ks * nt + t0 + tp) * 64] : make_uint4(0u, 0u, 0u, 0u);
-        }
-#pragma unroll
-        for (int f = 0; f < PW_PF; ++f) {
-            if (ks0 + f * stride >= ks_end) break;
-            const uint32_t v[16] = {rq[f][0].x, rq[f][0].y, rq[f][0].z, rq[f][0].w,
-                                    rq[f][1].x, rq[f][1].y, rq[f][1].z, rq[f][1].w,
-                                    rq[f][2].x, rq[f][2].y, rq[f][2].z, rq[f][2].w,
-                                    rq[f][3].x, rq[f][3].y, rq[f][3].z, rq[f][3].w};
-            v4i A[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    uint32_t w = 0;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) w |= ((v[4 * e + i] >> (7 * c)) & 0x7fu) << (8 * i);
-                    A[c][e] = (int)w;
-                }
-#pragma unroll
-            for (int tp = 0; tp < PW_NTP; ++tp) {
-                if (t0 + tp < nt) {
-                    v4i B;
-                    __builtin_memcpy(&B, &bq[f][tp], 16);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        acc[c][tp] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[c], B, acc[c][tp], 0, 0, 0);
-                }
-            }
-        }
+        StepBuf<PW_PF> b;
+        load_steps<PW_PF>(b, rp, iv, bt, nt, t0, ks0, ks_end, stride);
+        mma_steps<PW_PF>(b, nt, t0, ks0, ks_end, stride, acc);
     }
 }
 
