@@ -115,6 +115,31 @@ int dpm_moments_async(const void *volume, const int64_t dims[3], dpm_dtype dtype
 int dpm_project_images(const void *volume, const int64_t dims[3], dpm_dtype dtype,
                        int max_order, int32_t *images_device, void *stream);
 
+/* ---- object features (Section 4, after the moments) ---------------------------
+ * From the exact moments of one volume (eq. 2), for every moment of order <= max_order
+ * in graded order:
+ *   centroid   (x̄, ȳ, z̄) = (M100, M010, M001) / M000;
+ *   mu         central moments  mu_pqr = sum V (x - x̄)^p (y - ȳ)^q (z - z̄)^r;
+ *   eta        scale-normalised eta_pqr = mu_pqr / mu_000^((p+q+r)/3 + 1);
+ *   mu_phys    physical spacing mu'_pqr = alpha^(1+p) beta^(1+q) delta^(1+r) mu_pqr with
+ *              (alpha, beta, delta) = spacing (NULL: 1, 1, 1).
+ * M000^n mu_pqr (n = p+q+r) is formed as an exact integer on the device, so mu carries
+ * no cancellation error: it is the exact rational rounded twice to double (relative
+ * error below 2^-51; mu_100 = mu_010 = mu_001 = 0 exactly).  A volume of zero mass
+ * gives NaN for the centroid and for every moment of order >= 1 (mu_000 = M000 = 0).  Blocking; volume is a device pointer; out's arrays are HOST
+ * memory of dpm_num_moments(max_order) doubles (eta, mu_phys may be NULL).  Uses the
+ * library-owned workspace of the device.  DPM_ERANGE if the exact numerators would need
+ * more than 1024 bits (orders near 16 of volumes much larger than 512^3). */
+typedef struct {
+    double centroid[3];
+    double *mu;
+    double *eta;
+    double *mu_phys;
+} dpm_features_out;
+
+int dpm_features(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order,
+                 const double spacing[3], dpm_features_out *out);
+
 /* ---- batched regions of interest --------------------------------------------
  * Many independent volumes ("ROIs") in one packed device buffer; each ROI is its own
  * volume with its own origin (eq. 2 applied to the ROI).  ROI i starts at byte

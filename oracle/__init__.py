@@ -19,4 +19,6 @@ from .moments import (  # noqa: F401
     projection_image,
     image_moments_2d,
     central_moments,
+    central_from_raw,
+    features,
 )

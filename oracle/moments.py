@@ -13,6 +13,10 @@ written out in exact integer (or exact rational) arithmetic:
 * ``image_moments_2d``: the 2D moment sum of Section 1, eq. (1).
 * ``central_moments``: the central moments of Section 4 (centroid, then the
   translated sum), in exact rationals.
+* ``central_from_raw``: the same central moments from exact raw moments, by expanding
+  the three binomials of that sum (checked against ``central_moments``).
+* ``features``: centroid, central moments, the scale-normalised moments and the
+  physical-spacing moments of Section 4, from exact raw moments.
 
 Volumes are numpy arrays of shape (N, M, L) indexed V[z][y][x] (x contiguous, the
 memory order of the projection pseudo-code in Section 5).  Coordinates are 0-based as
@@ -36,6 +40,8 @@ __all__ = [
     "projection_image",
     "image_moments_2d",
     "central_moments",
+    "central_from_raw",
+    "features",
 ]
 
 
@@ -218,4 +224,58 @@ def central_moments(V, K):
         for v, a, b, c in zip(vals, zz, yy, xx):
             s += v * (int(c) - xbar) ** p * (int(b) - ybar) ** q * (int(a) - zbar) ** r
         out[(p, q, r)] = s
+    return out
+
+
+def central_from_raw(raw, K):
+    """Central moments of Section 4 from the exact raw moments ``raw`` (graded order, all
+    orders up to some order >= max(K, 1)), exact rationals: expanding (x - xbar)^p (y - ybar)^q (z - zbar)^r binomially,
+    mu_pqr = sum_{a<=p, b<=q, c<=r} C(p,a) C(q,b) C(r,c) (-xbar)^(p-a) (-ybar)^(q-b)
+    (-zbar)^(r-c) M_abc."""
+    from math import comb
+    kr = 0
+    while (kr + 1) * (kr + 2) * (kr + 3) // 6 < len(raw):
+        kr += 1
+    if (kr + 1) * (kr + 2) * (kr + 3) // 6 != len(raw) or kr < max(K, 1):
+        raise ValueError("raw must hold every moment of some order >= max(K, 1)")
+    M = {pqr: int(v) for pqr, v in zip(moment_list(kr), raw)}
+    m000 = M[(0, 0, 0)]
+    if m000 == 0:
+        raise ValueError("empty volume has no centroid")
+    xb, yb, zb = Fraction(M[(1, 0, 0)], m000), Fraction(M[(0, 1, 0)], m000), Fraction(M[(0, 0, 1)], m000)
+    out = {}
+    for (p, q, r) in moment_list(K):
+        s = Fraction(0)
+        for a in range(p + 1):
+            for b in range(q + 1):
+                for c in range(r + 1):
+                    s += (comb(p, a) * comb(q, b) * comb(r, c) * (-xb) ** (p - a) * (-yb) ** (q - b)
+                          * (-zb) ** (r - c) * M[(a, b, c)])
+        out[(p, q, r)] = s
+    return out
+
+
+def features(raw, K, spacing=(1, 1, 1)):
+    """The object features of Section 4 from exact raw moments (graded order):
+    centroid = (M100, M010, M001) / M000; mu = central moments (exact rationals);
+    eta_pqr = mu_pqr / mu_000^((p+q+r)/3 + 1), evaluated in 60-digit decimal arithmetic;
+    mu_phys_pqr = alpha^(1+p) beta^(1+q) delta^(1+r) mu_pqr with (alpha, beta, delta) =
+    spacing taken exactly.  Returns floats (nearest double of each quantity) and the
+    exact mu."""
+    from decimal import Decimal, localcontext
+    mu = central_from_raw(raw, K)
+    m000 = int(raw[0])
+    al, be, de = (Fraction(s) for s in spacing)
+    out = {"centroid": [float(Fraction(int(raw[i]), m000)) for i in (1, 2, 3)], "mu_exact": mu,
+           "mu": [], "eta": [], "mu_phys": []}
+    with localcontext() as ctx:
+        ctx.prec = 60
+        dm = Decimal(m000)
+        for (p, q, r) in moment_list(K):
+            v = mu[(p, q, r)]
+            n = p + q + r
+            out["mu"].append(float(v))
+            e = (Decimal(v.numerator) / Decimal(v.denominator)) / dm ** (Decimal(n) / Decimal(3) + 1)
+            out["eta"].append(float(e))
+            out["mu_phys"].append(float(al ** (1 + p) * be ** (1 + q) * de ** (1 + r) * v))
     return out

@@ -146,6 +146,22 @@ def moments_async(vol, K, out_exact, out_fp64, workspace, stream=None):
     check(rc, "dpm_moments_async")
 
 
+def features(vol, K, spacing=None):
+    """Centroid, central moments mu, normalised eta and spacing-scaled mu' of a device
+    volume for orders <= K (blocking).  Returns a dict of numpy arrays in graded order."""
+    _check_volume(vol)
+    nm = num_moments(K)
+    if nm < 0:
+        raise ValueError("max_order must be in [0, 16]")
+    mu, eta, mup = (np.empty(nm, dtype=np.float64) for _ in range(3))
+    out = _lib.FeaturesOut()
+    out.mu, out.eta, out.mu_phys = mu.ctypes.data, eta.ctypes.data, mup.ctypes.data
+    sp = (ctypes.c_double * 3)(*spacing) if spacing is not None else None
+    check(lib().dpm_features(ctypes.c_void_p(vol.data_ptr()), _dims_of_shape(vol.shape), _dtype_code(vol), int(K),
+                             sp, ctypes.byref(out)), "dpm_features")
+    return {"centroid": np.array(out.centroid[:]), "mu": mu, "eta": eta, "mu_phys": mup}
+
+
 def project_images(vol, K, stream=None):
     """The K+1 projection images as a list of int32 device tensors of shape (M, W_d)."""
     import torch

@@ -53,6 +53,11 @@ class PlanInfo(ctypes.Structure):
                 ("power_chunk", ctypes.c_int32)]
 
 
+class FeaturesOut(ctypes.Structure):
+    _fields_ = [("centroid", ctypes.c_double * 3), ("mu", ctypes.c_void_p), ("eta", ctypes.c_void_p),
+                ("mu_phys", ctypes.c_void_p)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("z_splits", ctypes.c_int32), ("power_chunk", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 2)]
@@ -114,6 +119,8 @@ SIGNATURES = {
     "dpm_tune_set": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(Tuning)]),
     "dpm_tune_clear": (ctypes.c_int, []),
+    "dpm_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.POINTER(FeaturesOut)]),
     "dpm_recomb_weight": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64)]),
     "dpm_profile_enable": (ctypes.c_int, [ctypes.c_int]),

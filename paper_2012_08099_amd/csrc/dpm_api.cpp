@@ -439,12 +439,13 @@ int ensure_buf(void *&ptr, size_t &have, size_t need) {
 }
 
 int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img_off,
-             const int64_t *img_w, void *exact, double *fp64, void *ws, hipStream_t st) {
+             const int64_t *img_w, void *exact, double *fp64, void *ws, hipStream_t st,
+             uint32_t *raw = nullptr) {
     uint8_t *base = static_cast<uint8_t *>(ws);
     int32_t *rows = reinterpret_cast<int32_t *>(base);
     uint32_t *part = reinterpret_cast<uint32_t *>(base + p.rows_bytes);
     PowTab pt{};
-    const bool moments = (exact || fp64);
+    const bool moments = (exact || fp64 || raw);
     if (p.mfma && moments) {
         int prc = get_powtab(p.amax, p.K, pt);
         if (prc) return prc;
@@ -516,6 +517,7 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
     for (int s = 0; s <= NSLOT; ++s) f.tile0[s] = p.rl.tile0[s];
     f.exact = exact;
     f.fp64 = fp64;
+    f.raw = raw;
     e = launch_finish(p.nlr, f, st);
     if (e != hipSuccess) return hip_fail(e);
     prof_mark(3, st);
@@ -669,6 +671,56 @@ int dpm_moments(const void *volume, const int64_t dims[3], dpm_dtype dtype, int 
         e = hipMemcpy(out->fp64, dfp, (size_t)nm * 8, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e);
     }
+    return DPM_OK;
+}
+
+int dpm_features(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order,
+                 const double spacing[3], dpm_features_out *out) {
+    if (!volume || !out || !out->mu || max_order < 0 || max_order > KMAX) return DPM_EINVAL;
+    if (spacing && !(spacing[0] > 0 && spacing[1] > 0 && spacing[2] > 0)) return DPM_EINVAL;
+    if (int trc = ensure_device_tables()) return trc;
+    // the centroid needs the first-order moments whatever the order asked for
+    const int kr = std::max(max_order, 1);
+    Plan p;
+    int rc = make_plan(dims, dtype, kr, false, p, volume);
+    if (rc) return rc;
+    // width of the exact numerators: |M000^n mu| < 2^n M000^(n+1) D^n, D = largest coordinate
+    const uint64_t vmax = p.elem == 1 ? 255u : 65535u;
+    const int b000 = bitlen_u64(vmax) + bitlen_u64((uint64_t)p.L) + bitlen_u64((uint64_t)p.M) +
+                     bitlen_u64((uint64_t)p.N);
+    const int bd = bitlen_u64((uint64_t)std::max<int64_t>(std::max(p.L, p.M), p.N));
+    const int bits = max_order + (max_order + 1) * b000 + max_order * bd + 2;
+    const int w = (bits + 31) / 32;
+    if (w > 32) return DPM_ERANGE;
+    int dev;
+    if ((rc = current_device(dev))) return rc;
+    const int nm = n_moments(max_order);
+    const size_t raw_bytes = align_up((size_t)n_moments(kr) * p.nlr * 4), d_bytes = align_up((size_t)(3 + 3 * nm) * 8);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    if ((rc = ensure_buf(g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
+    if ((rc = ensure_buf(g_ws[dev].out, g_ws[dev].out_bytes, raw_bytes + d_bytes))) return rc;
+    uint8_t *ob = static_cast<uint8_t *>(g_ws[dev].out);
+    uint32_t *draw = reinterpret_cast<uint32_t *>(ob);
+    double *dd = reinterpret_cast<double *>(ob + raw_bytes);
+    rc = run_plan(p, volume, nullptr, nullptr, nullptr, nullptr, nullptr, g_ws[dev].ptr, nullptr, draw);
+    if (rc) return rc;
+    FeatArgs f{};
+    f.raw = draw;
+    f.K = max_order;
+    for (int i = 0; i < 3; ++i) f.spacing[i] = spacing ? spacing[i] : 1.0;
+    f.centroid = dd;
+    f.mu = dd + 3;
+    f.eta = dd + 3 + nm;
+    f.mu_phys = dd + 3 + 2 * nm;
+    hipError_t e = launch_features(p.nlr, w, f, nullptr);
+    if (e != hipSuccess) return hip_fail(e);
+    if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e);
+    std::vector<double> h((size_t)3 + 3 * nm);
+    if ((e = hipMemcpy(h.data(), dd, h.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e);
+    for (int i = 0; i < 3; ++i) out->centroid[i] = h[i];
+    std::memcpy(out->mu, h.data() + 3, (size_t)nm * 8);
+    if (out->eta) std::memcpy(out->eta, h.data() + 3 + nm, (size_t)nm * 8);
+    if (out->mu_phys) std::memcpy(out->mu_phys, h.data() + 3 + 2 * nm, (size_t)nm * 8);
     return DPM_OK;
 }
 

@@ -122,8 +122,20 @@ struct FinishArgs {
     int32_t tile0[NSLOT + 1];  // single volume: tiles of slot s are [tile0[s], tile0[s+1])
     void *exact;               // dpm_i128 [vol][n_moments(min(K,4))] or null
     double *fp64;              // [vol][n_moments(K)] or null
+    uint32_t *raw;             // exact moments, NLR 32-bit limbs each, [vol][n_moments(K)], or null
 };
 hipError_t launch_finish(int nlr, const FinishArgs &a, hipStream_t st);
+
+// Features of one volume from its exact moments (FinishArgs::raw, nlr limbs each), in w
+// limbs; outputs are device arrays of n_moments(K) doubles (eta, mu_phys optional).
+struct FeatArgs {
+    const uint32_t *raw;
+    int32_t K;
+    double spacing[3];
+    double *centroid;          // 3 or null
+    double *mu, *eta, *mu_phys;
+};
+hipError_t launch_features(int nlr, int w, const FeatArgs &f, hipStream_t st);
 
 // recombination tables (host side generation, device upload)
 struct RecombTables {

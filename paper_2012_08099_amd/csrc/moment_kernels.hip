@@ -125,6 +125,9 @@ __global__ void __launch_bounds__(NT) finish_kernel(FinishArgs a) {
     const mw::Int<NLR> val = mw::mul_mod(num, inv);
     const int nm = n_moments(K), nm4 = n_moments(K < 4 ? K : 4);
     if (a.fp64) a.fp64[(size_t)vol * nm + m] = mw::to_double(val);
+    if (a.raw)
+#pragma unroll
+        for (int l = 0; l < NLR; ++l) a.raw[((size_t)vol * nm + m) * NLR + l] = val.w[l];
     if (a.exact && m < nm4) {
         uint64_t *e = reinterpret_cast<uint64_t *>(a.exact) + 2 * ((size_t)vol * nm4 + m);
         e[0] = (uint64_t)val.w[0] | ((uint64_t)val.w[1] << 32);

@@ -302,3 +302,63 @@ def test_moment_single_matches():
     m = as_dict(moments_exact(V, 6), 6)
     for t in [(0, 0, 0), (6, 0, 0), (0, 6, 0), (0, 0, 6), (2, 2, 2), (1, 3, 2)]:
         assert moment_single(V, *t) == m[t]
+
+
+# ---- features of Section 4 (centroid, central, normalised, physical-spacing moments)
+
+@pytest.mark.parametrize("seed", range(4))
+def test_central_from_raw_equals_definition(seed):
+    """The binomial expansion from raw moments equals the direct translated sum."""
+    rng = np.random.default_rng(seed)
+    V = rng.integers(0, 9, size=tuple(int(s) for s in rng.integers(1, 6, size=3))).astype(np.uint8)
+    V[0, 0, 0] += 1  # non-zero mass
+    K = 5
+    assert oracle.central_from_raw(oracle.moments_exact(V, K), K) == oracle.central_moments(V, K)
+
+
+def test_central_moments_of_a_box_closed_form():
+    """A uniform box: mu_pqr = c * S_p(L) S_q(M) S_r(N), S_k(n) = sum_{x<n} (x - (n-1)/2)^k
+    (zero for odd k)."""
+    from fractions import Fraction
+    N, M, L, c = 5, 4, 7, 3
+    V = np.full((N, M, L), c, dtype=np.uint8)
+    K = 6
+
+    def S(k, n):
+        return sum((Fraction(x) - Fraction(n - 1, 2)) ** k for x in range(n))
+
+    mu = oracle.central_from_raw(oracle.moments_exact(V, K), K)
+    for (p, q, r), v in mu.items():
+        assert v == c * S(p, L) * S(q, M) * S(r, N), (p, q, r)
+        if p % 2 or q % 2 or r % 2:
+            assert v == 0
+
+
+def test_features_eta_and_spacing_definitions():
+    from fractions import Fraction
+    V = np.random.default_rng(3).integers(0, 50, size=(6, 5, 7)).astype(np.uint8)
+    K = 4
+    raw = oracle.moments_exact(V, K)
+    f = oracle.features(raw, K, spacing=(2.0, 3.0, 0.5))
+    idx = {pqr: i for i, pqr in enumerate(oracle.moment_list(K))}
+    m000 = int(raw[0])
+    assert f["eta"][idx[(0, 0, 0)]] == 1.0
+    assert f["mu"][idx[(1, 0, 0)]] == f["mu"][idx[(0, 1, 0)]] == f["mu"][idx[(0, 0, 1)]] == 0.0
+    assert f["centroid"][0] == float(Fraction(int(raw[idx[(1, 0, 0)]]), m000))
+    for (p, q, r), i in idx.items():
+        mu = f["mu_exact"][(p, q, r)]
+        assert f["mu_phys"][i] == float(Fraction(2) ** (1 + p) * Fraction(3) ** (1 + q) * Fraction(1, 2) ** (1 + r) * mu)
+        n = p + q + r
+        assert abs(f["eta"][i] - float(mu) / m000 ** (n / 3 + 1)) <= 1e-12 * max(abs(f["eta"][i]), 1e-300)
+    g = oracle.features(raw, K)
+    assert g["mu_phys"] == g["mu"]
+
+
+def test_features_order_zero_uses_first_order_raw_moments():
+    V = np.random.default_rng(5).integers(0, 9, size=(3, 4, 5)).astype(np.uint8)
+    V[1, 1, 1] += 1
+    raw = oracle.moments_exact(V, 1)
+    f = oracle.features(raw, 0)
+    assert f["mu"] == [float(raw[0])] and f["eta"] == [1.0]
+    with pytest.raises(ValueError):
+        oracle.central_from_raw(raw[:1], 0)
