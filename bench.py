@@ -367,6 +367,13 @@ def main(argv=None):
                   "ms_best": r["best"]["ms"], "ms_planner_default": default["ms"],
                   "candidates": len(r["candidates"]), "seconds": time.perf_counter() - t0}
         log("tuning", tuning)
+    # object features (Section 4) of volume 0: blocking calls (moments + features kernel +
+    # copies), timed on the host; before the warmup so the timed phases are undisturbed
+    dpm.features(vols[0], K)
+    t0 = time.perf_counter()
+    for _ in range(5):
+        feats = dpm.features(vols[0], K)
+    features_ms = (time.perf_counter() - t0) / 5 * 1e3
     depth = max(1, a.streams)
     wsb = dpm.workspace_bytes(shape, code, K)
     ws = [torch.empty(wsb, dtype=torch.uint8, device="cuda:0") for _ in range(depth)]
@@ -451,6 +458,7 @@ def main(argv=None):
                      "algorithmic_bytes_per_launch": bytes_launch},
         "source_hash": shash,
         "tuning": tuning,
+        "features": {"call_ms_blocking": features_ms, "centroid": [float(c) for c in feats["centroid"]]},
         "plan": {k: plan[k] for k in ("z_splits", "n_items", "power_tiles", "power_chunk")},
     }
     if not a.no_cpu_baseline:
