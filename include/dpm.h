@@ -115,6 +115,17 @@ int dpm_moments_async(const void *volume, const int64_t dims[3], dpm_dtype dtype
 int dpm_project_images(const void *volume, const int64_t dims[3], dpm_dtype dtype,
                        int max_order, int32_t *images_device, void *stream);
 
+/* Moments from supplied projection images instead of a volume (Section 3.2: chosen
+ * tomographic projections can stand in for a full reconstruction).  images_device holds
+ * the max_order+1 images exactly as dpm_project_images writes them for a volume of dims
+ * and dtype (image d = [y][i], M rows of dpm_image_width(dims, d) int32, one after the
+ * other; beta < 0 images carry the offset |beta| (N-1)).  The images are read only:
+ * every entry must be a line sum of such a volume, 0 <= entry <= vmax * max(L, N)
+ * (vmax 255 / 65535), else DPM_ERANGE (the result is then not written).  Blocking; out's
+ * arrays are HOST memory as for dpm_moments; uses the library-owned workspace. */
+int dpm_moments_from_images(const int32_t *images_device, const int64_t dims[3], dpm_dtype dtype,
+                            int max_order, dpm_out *out);
+
 /* ---- object features (Section 4, after the moments) ---------------------------
  * From the exact moments of one volume (eq. 2), for every moment of order <= max_order
  * in graded order:

@@ -146,6 +146,24 @@ def moments_async(vol, K, out_exact, out_fp64, workspace, stream=None):
     check(rc, "dpm_moments_async")
 
 
+def moments_from_images(images, shape, dtype_code, K):
+    """Moments from the K+1 projection images of a (N, M, L) = ``shape`` volume (blocking).
+    ``images``: one contiguous int32 device tensor in the layout of ``project_images``."""
+    import torch
+    if not images.is_cuda or images.dtype != torch.int32 or not images.is_contiguous():
+        raise ValueError("images must be a contiguous int32 device tensor")
+    nm, nm4 = num_moments(K), num_moments(min(K, 4))
+    if nm < 0:
+        raise ValueError("max_order must be in [0, 16]")
+    ex = np.zeros((nm4, 2), dtype=np.int64)
+    fp = np.zeros(nm, dtype=np.float64)
+    out = Out(ex.ctypes.data, fp.ctypes.data)
+    check(lib().dpm_moments_from_images(ctypes.c_void_p(images.data_ptr()), _dims_of_shape(shape), int(dtype_code),
+                                        int(K), ctypes.byref(out)), "dpm_moments_from_images")
+    exact = [int(lo) | (int(hi) << 64) for lo, hi in zip(ex[:, 0].astype(np.uint64).tolist(), ex[:, 1].tolist())]
+    return Moments(K, exact, fp)
+
+
 def features(vol, K, spacing=None):
     """Centroid, central moments mu, normalised eta and spacing-scaled mu' of a device
     volume for orders <= K (blocking).  Returns a dict of numpy arrays in graded order."""

@@ -119,6 +119,8 @@ SIGNATURES = {
     "dpm_tune_set": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(Tuning)]),
     "dpm_tune_clear": (ctypes.c_int, []),
+    "dpm_moments_from_images": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
+                                               ctypes.c_int, ctypes.POINTER(Out)]),
     "dpm_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
                                     ctypes.c_void_p, ctypes.POINTER(FeaturesOut)]),
     "dpm_recomb_weight": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,

@@ -440,7 +440,7 @@ int ensure_buf(void *&ptr, size_t &have, size_t need) {
 
 int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img_off,
              const int64_t *img_w, void *exact, double *fp64, void *ws, hipStream_t st,
-             uint32_t *raw = nullptr) {
+             uint32_t *raw = nullptr, const ImgArgs *from_images = nullptr) {
     uint8_t *base = static_cast<uint8_t *>(ws);
     int32_t *rows = reinterpret_cast<int32_t *>(base);
     uint32_t *part = reinterpret_cast<uint32_t *>(base + p.rows_bytes);
@@ -451,7 +451,14 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
         if (prc) return prc;
     }
     if (moments) prof_mark(0, st);
-    if (p.one_launch && !images) {
+    if (from_images) {
+        // step 1 replaced by supplied images: gather them into the row slots
+        ImgArgs ia = *from_images;
+        ia.rows = rows;
+        ia.rl = p.rl;
+        hipError_t e = launch_images_to_rows(ia, st);
+        if (e != hipSuccess) return hip_fail(e);
+    } else if (p.one_launch && !images) {
         // orders 7-16: every direction group in one launch, sibling workgroups per item
         SliceArgs a{};
         a.vol = static_cast<const uint8_t *>(vol);
@@ -471,7 +478,7 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
         hipError_t e = launch_slice_groups(p.elem, p.nd, a, p.items, lds, st);
         if (e != hipSuccess) return hip_fail(e);
     }
-    for (int g = 0; g < p.ngroups && !(p.one_launch && !images); ++g) {
+    for (int g = 0; g < p.ngroups && !from_images && !(p.one_launch && !images); ++g) {
         SliceArgs a{};
         a.vol = static_cast<const uint8_t *>(vol);
         a.L = p.L;
@@ -744,6 +751,53 @@ int dpm_project_images(const void *volume, const int64_t dims[3], dpm_dtype dtyp
     if ((rc = ensure_buf(g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
     return run_plan(p, volume, images_device, off, w, nullptr, nullptr, g_ws[dev].ptr,
                     static_cast<hipStream_t>(stream));
+}
+
+int dpm_moments_from_images(const int32_t *images_device, const int64_t dims[3], dpm_dtype dtype,
+                            int max_order, dpm_out *out) {
+    if (!images_device || !out) return DPM_EINVAL;
+    if (int trc = ensure_device_tables()) return trc;
+    Plan p;
+    int rc = make_plan(dims, dtype, max_order, true, p, nullptr);
+    if (rc) return rc;
+    ImgArgs ia{};
+    ia.images = images_device;
+    ia.nd = p.nd;
+    ia.M = (int32_t)p.M;
+    int64_t acc = 0;
+    for (int d = 0; d < p.nd; ++d) {
+        const int64_t w = dpm_image_width(dims, d);
+        ia.off[d] = acc;
+        ia.width[d] = (int32_t)w;
+        ia.origin[d] = dir_beta(d) < 0 ? (int32_t)(-dir_beta(d) * (p.N - 1)) : 0;
+        acc += w * p.M;
+    }
+    // every entry is a line sum: at most max(L, N) voxels of at most vmax
+    ia.bound = (int64_t)(p.elem == 1 ? 255 : 65535) * std::max(p.L, p.N);
+    int dev;
+    if ((rc = current_device(dev))) return rc;
+    const int nm = n_moments(max_order), nm4 = n_moments(std::min(max_order, 4));
+    const size_t ex_bytes = align_up((size_t)nm4 * 16), fp_bytes = align_up((size_t)nm * 8);
+    std::lock_guard<std::recursive_mutex> lk(g_mu);
+    if ((rc = ensure_buf(g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
+    if ((rc = ensure_buf(g_ws[dev].out, g_ws[dev].out_bytes, ex_bytes + fp_bytes + 256))) return rc;
+    uint8_t *ob = static_cast<uint8_t *>(g_ws[dev].out);
+    void *dex = ob;
+    double *dfp = reinterpret_cast<double *>(ob + ex_bytes);
+    ia.bad = reinterpret_cast<uint32_t *>(ob + ex_bytes + fp_bytes);
+    hipError_t e = hipMemsetAsync(ia.bad, 0, 4, nullptr);
+    if (e != hipSuccess) return hip_fail(e);
+    rc = run_plan(p, nullptr, nullptr, nullptr, nullptr, dex, dfp, g_ws[dev].ptr, nullptr, nullptr, &ia);
+    if (rc) return rc;
+    uint32_t bad = 0;
+    if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e);
+    if ((e = hipMemcpy(&bad, ia.bad, 4, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e);
+    if (bad) return DPM_ERANGE;
+    if (out->exact && (e = hipMemcpy(out->exact, dex, (size_t)nm4 * 16, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e);
+    if (out->fp64 && (e = hipMemcpy(out->fp64, dfp, (size_t)nm * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e);
+    return DPM_OK;
 }
 
 int dpm_tune_set(const int64_t dims[3], dpm_dtype dtype, int max_order, const dpm_tuning *t) {

@@ -126,6 +126,22 @@ struct FinishArgs {
 };
 hipError_t launch_finish(int nlr, const FinishArgs &a, hipStream_t st);
 
+// Moments from supplied projection images: image d (the layout of dpm_project_images)
+// gathered into the row slots of item y = one image row, split at the origin.  Entries
+// outside [0, bound] are replaced by 0 and reported in *bad.
+struct ImgArgs {
+    const int32_t *images;
+    int64_t off[NDIR_MAX];     // int32 offset of image d
+    int32_t width[NDIR_MAX];
+    int32_t origin[NDIR_MAX];  // column of the true origin, |beta| (N-1) for beta < 0
+    int32_t nd, M;
+    int64_t bound;
+    int32_t *rows;
+    RowLayout rl;
+    uint32_t *bad;
+};
+hipError_t launch_images_to_rows(const ImgArgs &a, hipStream_t st);
+
 // Features of one volume from its exact moments (FinishArgs::raw, nlr limbs each), in w
 // limbs; outputs are device arrays of n_moments(K) doubles (eta, mu_phys optional).
 struct FeatArgs {
