@@ -374,6 +374,15 @@ def main(argv=None):
     for _ in range(5):
         feats = dpm.features(vols[0], K)
     features_ms = (time.perf_counter() - t0) / 5 * 1e3
+    # moments from supplied projection images (the volume's own, projected once)
+    flat = torch.cat([im.reshape(-1) for im in dpm.project_images(vols[0], K)]).contiguous()
+    fi = dpm.moments_from_images(flat, shape, code, K)
+    assert fi.exact == dpm.moments(vols[0], K).exact
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dpm.moments_from_images(flat, shape, code, K)
+    from_images_ms = (time.perf_counter() - t0) / 5 * 1e3
+    del flat
     depth = max(1, a.streams)
     wsb = dpm.workspace_bytes(shape, code, K)
     ws = [torch.empty(wsb, dtype=torch.uint8, device="cuda:0") for _ in range(depth)]
@@ -459,6 +468,7 @@ def main(argv=None):
         "source_hash": shash,
         "tuning": tuning,
         "features": {"call_ms_blocking": features_ms, "centroid": [float(c) for c in feats["centroid"]]},
+        "from_images": {"call_ms_blocking": from_images_ms},
         "plan": {k: plan[k] for k in ("z_splits", "n_items", "power_tiles", "power_chunk")},
     }
     if not a.no_cpu_baseline:
