@@ -105,6 +105,69 @@ def cpu_baseline(V, K, target_s=12.0):
                       f"exact int128, {what} ({dt:.1f} s)"}
 
 
+# The paper's Table 1: DPM times (ms) on an Intel Core i5 (7th generation) for 1-byte
+# volumes of 1 ... 1024 MB at 3rd / 4th order -- context only, other hardware and data.
+TABLE1_MB = (1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024)
+TABLE1_MS = {3: (0.30, 0.56, 1.00, 2.00, 4.03, 8.25, 17.60, 37.5, 63.5, 130.4, 273.5),
+             4: (0.44, 0.90, 1.46, 2.75, 5.3, 10.95, 21.23, 41.0, 84.6, 173.8, 400.1)}
+# (N, M, L) of each size: 128 x 128 x 64 (the table's 1 MB volume), then doubling one axis
+TABLE1_SHAPES = ((64, 128, 128), (128, 128, 128), (128, 128, 256), (128, 256, 256), (256, 256, 256),
+                 (256, 256, 512), (256, 512, 512), (512, 512, 512), (512, 512, 1024), (512, 1024, 1024),
+                 (1024, 1024, 1024))
+
+
+def sweep_main(a):
+    """The sizes of the paper's Table 1 on one GPU: uniform random uint8 volumes of 1-1024 MB
+    at orders 3 and 4; per volume the single-stream time of one dpm_moments_async call
+    (HIP events over 10 calls), beside the paper's CPU times and, up to 64 MB, the naive
+    direct-sum oracle on this host's cores."""
+    import numpy as np
+    import torch
+
+    import paper_2012_08099_amd as dpm
+    rows = []
+    for mb, shape in zip(TABLE1_MB, TABLE1_SHAPES):
+        V = np.random.default_rng(mb).integers(0, 256, size=shape, dtype=np.uint8)
+        vol = torch.from_numpy(V).to("cuda:0")
+        for K in (3, 4):
+            nm, nm4 = dpm.num_moments(K), dpm.num_moments(min(K, 4))
+            ws = torch.empty(dpm.workspace_bytes(shape, 1, K), dtype=torch.uint8, device="cuda:0")
+            ex = torch.empty((nm4, 2), dtype=torch.int64, device="cuda:0")
+            fp = torch.empty(nm, dtype=torch.float64, device="cuda:0")
+            for _ in range(3):
+                dpm.moments_async(vol, K, ex, fp, ws)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                dpm.moments_async(vol, K, ex, fp, ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 10
+            row = {"mb": mb, "shape_zyx": list(shape), "K": K, "gpu_ms": ms, "gpu_voxels_per_s": V.size / (ms / 1e3),
+                   "hbm_frac": V.size / (ms / 1e3) / (HBM_PEAK_GBS * 1e9), "paper_cpu_ms": TABLE1_MS[K][TABLE1_MB.index(mb)]}
+            if mb <= 64 and not a.no_cpu_baseline:
+                import oracle.native as onative
+                onative.build(force=False)
+                t0 = time.perf_counter()
+                ref = onative.moments_direct(V, K)
+                row["naive_cpu_ms"] = (time.perf_counter() - t0) * 1e3
+                assert [int(v) for v in ref[:nm4]] == dpm._exact_from_tensor(ex)
+            rows.append(row)
+            log(row)
+        del vol
+    big = [r for r in rows if r["mb"] == 1024 and r["K"] == 4][0]
+    out = {"metric": "voxels/s (1024^3 uint8, orders <= 4; the paper's Table 1 sizes)", "value": big["gpu_voxels_per_s"],
+           "unit": "voxels/s", "n_gpus": 1, "steps": 10, "warmup": 3, "ms_per_step": big["gpu_ms"],
+           "higher_is_better": True, "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": "table1_sweep: uniform random uint8 volumes of 1-1024 MB, orders 3 and 4"},
+           "cpu_cores": None, "sweep": rows}
+    if not a.no_cpu_baseline:
+        import oracle.native as onative
+        out["cpu_cores"] = onative.num_threads()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def read_traffic(workload, shash):
     p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(p):
@@ -312,7 +375,8 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="ct512_k6", choices=sorted(WORKLOADS) + ["serve_mix", "rois1000"])
+    ap.add_argument("--workload", default="ct512_k6",
+                    choices=sorted(WORKLOADS) + ["serve_mix", "rois1000", "table1_sweep"])
     ap.add_argument("--requests", type=int, default=10000, help="serve_mix: requests per run; rois1000: ROIs")
     ap.add_argument("--hbm-budget", type=int, default=16, help="serve_mix: server arena, GiB")
     ap.add_argument("--server-streams", type=int, default=4, help="serve_mix: server streams")
@@ -333,6 +397,8 @@ def main(argv=None):
 
     if a.workload == "serve_mix":
         return serve_main(a)
+    if a.workload == "table1_sweep":
+        return sweep_main(a)
     if a.workload == "rois1000":
         if a.requests == 10000:
             a.requests = 1000
