@@ -101,7 +101,11 @@ int dpm_moments(const void *volume, const int64_t dims[3], dpm_dtype dtype, int 
 /* Stream-ordered call.  volume, out_device->exact/fp64 and workspace are device
  * pointers; workspace must hold dpm_workspace_bytes() bytes (NULL = use the
  * library-owned workspace of this device, which serialises callers).  Returns after
- * enqueueing; results are valid once `stream` reaches this point. */
+ * enqueueing; results are valid once `stream` reaches this point.
+ * Graph capture: with a caller workspace, and once an eager call of the same dims, dtype
+ * and order has run on the device (it builds the device tables), the call enqueues
+ * kernels only -- no allocation, no memset, every byte it reads written first -- so a
+ * caller may capture it into a HIP graph and replay it (new voxels in place included). */
 int dpm_moments_async(const void *volume, const int64_t dims[3], dpm_dtype dtype,
                       int max_order, const dpm_out *out_device, void *workspace,
                       size_t ws_bytes, void *stream);

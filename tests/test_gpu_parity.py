@@ -371,3 +371,41 @@ def test_batched_refuses_rows_beyond_lds(dpm):
                                        ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
     assert rc == -2
     assert_moments_equal(dpm.moments(to_dev(V), 6), oracle.moments_exact(V, 6), 6, "4096 column")
+
+
+def test_moments_async_replayed_from_a_captured_graph(dpm):
+    """A caller may capture dpm_moments_async (caller-owned workspace and outputs, its
+    tables built by an earlier eager call) into a HIP graph: every replay, with eager
+    library work and synchronisations between replays, equals the eager result, and new
+    voxels written in place give the new volume's moments."""
+    import torch
+    say("graph capture of dpm_moments_async")
+    K = 6
+    V = synth.ct_phantom((48, 40, 128), seed=4)
+    W = synth.mri_phantom((32, 24, 64), seed=6)
+    vol = to_dev(V)
+    nm, nm4 = dpm.num_moments(K), dpm.num_moments(4)
+    ex = torch.zeros((nm4, 2), dtype=torch.int64, device="cuda:0")
+    fp = torch.zeros(nm, dtype=torch.float64, device="cuda:0")
+    ws = torch.empty(dpm.workspace_bytes(V.shape, 2, K), dtype=torch.uint8, device="cuda:0")
+    dpm.moments_async(vol, K, ex, fp, ws)  # eager: builds the device tables
+    torch.cuda.synchronize()
+    ref_ex, ref_fp = ex.clone(), fp.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        dpm.moments_async(vol, K, ex, fp, ws, stream=torch.cuda.current_stream())
+    for i in range(4):
+        ex.zero_()
+        fp.zero_()
+        torch.cuda.synchronize()
+        other = dpm.moments(to_dev(W), 3)  # eager library work between replays
+        assert_moments_equal(other, oracle.moments_exact(W, 3), 3, f"eager between replays {i}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(ex, ref_ex) and torch.equal(fp.view(torch.int64), ref_fp.view(torch.int64)), i
+    V2 = synth.uniform_volume(V.shape, np.uint16, seed=8, hi=4095)
+    vol.copy_(to_dev(V2))
+    g.replay()
+    torch.cuda.synchronize()
+    got = dpm.Moments(K, dpm._exact_from_tensor(ex), fp.cpu().numpy())
+    assert_moments_equal(got, oracle.moments_exact(V2, K), K, "replay on new voxels")
