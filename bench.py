@@ -428,8 +428,8 @@ def main(argv=None):
         from paper_2012_08099_amd import autotune
         t0 = time.perf_counter()
         r = autotune.tune(vols[0], K, reps=20, warmup=3)
-        default = [c for c in r["candidates"] if c["z_splits"] == 0 and c["power_chunk"] == 0][0]
-        tuning = {"z_splits": r["best"]["z_splits"], "power_chunk": r["best"]["power_chunk"],
+        default = [c for c in r["candidates"] if c["z_splits"] == 0 and c["power_chunk"] == 0 and c["waves"] == 0][0]
+        tuning = {"z_splits": r["best"]["z_splits"], "power_chunk": r["best"]["power_chunk"], "waves": r["best"]["waves"],
                   "ms_best": r["best"]["ms"], "ms_planner_default": default["ms"],
                   "candidates": len(r["candidates"]), "seconds": time.perf_counter() - t0}
         log("tuning", tuning)
@@ -535,7 +535,7 @@ def main(argv=None):
         "tuning": tuning,
         "features": {"call_ms_blocking": features_ms, "centroid": [float(c) for c in feats["centroid"]]},
         "from_images": {"call_ms_blocking": from_images_ms},
-        "plan": {k: plan[k] for k in ("z_splits", "n_items", "power_tiles", "power_chunk")},
+        "plan": {k: plan[k] for k in ("z_splits", "n_items", "power_tiles", "power_chunk", "proj_waves")},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(V0, K)

@@ -321,28 +321,33 @@ typedef struct {
     int64_t workspace;     /* bytes                                           */
     int32_t power_tiles;   /* workgroups of the power-sum kernel              */
     int32_t power_chunk;   /* steps of 64 values of a per power tile (0: rows) */
+    int32_t proj_waves;    /* waves per workgroup of the first projection launch */
+    int32_t reserved;
 } dpm_plan_info;
 
 int dpm_plan(const int64_t dims[3], dpm_dtype dtype, int max_order, dpm_plan_info *info);
 
 /* ---- tuning ---------------------------------------------------------------------
- * Per-shape overrides of two planner choices, installed by an autotuner (the Python
+ * Per-shape overrides of three planner choices, installed by an autotuner (the Python
  * package's `autotune` module times the candidates through dpm_moments_async and
  * installs the fastest).  Both change how the work is split, never the result.
  *   z_splits:    work items per y-slice (each projection workgroup takes a z range);
  *                0 = the planner's choice.
  *   power_chunk: steps of 64 values of a per power-sum tile on the matrix cores;
  *                0 = the planner's choice, -1 = whole rows.
+ *   waves:       waves per projection workgroup of the first direction group when
+ *                whole rows are loaded: 0 = the planner's choice (4), 4 or 8.
  * An override applies to every later plan of exactly these dims, dtype and order, and
  * to the workspace size reported for them (query dpm_workspace_bytes after setting
  * it).  The environment overrides DPM_ZSPLITS / DPM_PW_KCHUNK take precedence.
  * t == NULL removes the override of this shape; dpm_tune_clear removes all.
- * Errors: DPM_EINVAL for bad dims, dtype, order, z_splits outside [0, 4096] or
- * power_chunk outside [-1, 4096]. */
+ * Errors: DPM_EINVAL for bad dims, dtype, order, z_splits outside [0, 4096],
+ * power_chunk outside [-1, 4096] or waves not 0, 4 or 8. */
 typedef struct {
     int32_t z_splits;
     int32_t power_chunk;
-    int32_t reserved[2];
+    int32_t waves;
+    int32_t reserved;
 } dpm_tuning;
 
 int dpm_tune_set(const int64_t dims[3], dpm_dtype dtype, int max_order, const dpm_tuning *t);

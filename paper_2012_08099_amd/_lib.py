@@ -50,7 +50,7 @@ class PlanInfo(ctypes.Structure):
                 ("limbs_moment", ctypes.c_int32), ("bits_slice", ctypes.c_int32),
                 ("bits_moment", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
                 ("workspace", ctypes.c_int64), ("power_tiles", ctypes.c_int32),
-                ("power_chunk", ctypes.c_int32)]
+                ("power_chunk", ctypes.c_int32), ("proj_waves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class FeaturesOut(ctypes.Structure):
@@ -59,8 +59,8 @@ class FeaturesOut(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("z_splits", ctypes.c_int32), ("power_chunk", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+    _fields_ = [("z_splits", ctypes.c_int32), ("power_chunk", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):

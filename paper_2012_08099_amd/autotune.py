@@ -1,13 +1,15 @@
 """Autotuner for the planner's work split, through the C ABI.
 
-Two planner choices change how one volume's work is divided, never its result:
+Three planner choices change how one volume's work is divided, never its result:
 
 * ``z_splits``: projection work items per y-slice (each workgroup projects a z range of
   one slice; more splits mean more workgroups and more image rows to sum);
 * ``power_chunk``: steps of 64 coordinates per power-sum tile on the matrix cores (smaller
-  chunks mean more, shorter workgroups and more tile partials to combine).
+  chunks mean more, shorter workgroups and more tile partials to combine);
+* ``waves``: waves per projection workgroup (first direction group, whole-row loads): 8
+  helps when there are too few slices to fill the CUs.
 
-``tune`` times every candidate pair with ``dpm_moments_async`` on one stream (HIP events
+``tune`` times every candidate triple with ``dpm_moments_async`` on one stream (HIP events
 around ``reps`` calls), requires each candidate's moments to be bit-identical to the
 planner's default, installs the fastest with ``dpm_tune_set`` and returns the timings.
 Results can be kept in a JSON file (``save`` / ``load``) keyed by shape, dtype and order,
@@ -24,11 +26,12 @@ from . import _dims_of_shape, _dtype_code, check, lib, moments_async, num_moment
 
 Z_SPLITS = (0, 1, 2, 4, 8)        # 0: the planner's choice
 POWER_CHUNKS = (0, 4, 8, 16, -1)  # 0: the planner's choice, -1: whole rows
+WAVES = (0, 8)                    # 0: the planner's choice (4)
 
 
-def set_tuning(shape, dtype_code, K, z_splits=0, power_chunk=0):
+def set_tuning(shape, dtype_code, K, z_splits=0, power_chunk=0, waves=0):
     """Install an override for volumes of numpy shape (N, M, L), dtype code and order K."""
-    t = _lib.Tuning(int(z_splits), int(power_chunk))
+    t = _lib.Tuning(int(z_splits), int(power_chunk), int(waves))
     check(lib().dpm_tune_set(_dims_of_shape(shape), int(dtype_code), int(K), ctypes.byref(t)), "dpm_tune_set")
 
 
@@ -45,11 +48,11 @@ def _key(shape, dtype_code, K):
     return f"{L}x{M}x{N}:{int(dtype_code)}:{int(K)}"
 
 
-def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS, stream=None):
-    """Measure every (z_splits, power_chunk) candidate on the device volume ``vol``
+def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS, waves=WAVES, stream=None):
+    """Measure every (z_splits, power_chunk, waves) candidate on the device volume ``vol``
     ((N, M, L) uint8, or uint16 carried as int16) and install the fastest.
 
-    Returns {"best": {...}, "candidates": [{"z_splits", "power_chunk", "ms"}, ...]}."""
+    Returns {"best": {...}, "candidates": [{"z_splits", "power_chunk", "waves", "ms"}, ...]}."""
     import torch
     code = _dtype_code(vol)
     shape = tuple(vol.shape)
@@ -82,12 +85,13 @@ def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS
     results = []
     for zs in z_splits:
         for pc in power_chunks:
-            ms, ex, fp = run((zs, pc))
-            if not (torch.equal(ex, ref_ex) and torch.equal(fp.view(torch.int64), ref_fp.view(torch.int64))):
-                raise RuntimeError(f"tuning candidate z_splits={zs} power_chunk={pc} changed the result")
-            results.append({"z_splits": zs, "power_chunk": pc, "ms": ms})
+            for w in waves:
+                ms, ex, fp = run((zs, pc, w))
+                if not (torch.equal(ex, ref_ex) and torch.equal(fp.view(torch.int64), ref_fp.view(torch.int64))):
+                    raise RuntimeError(f"tuning candidate z_splits={zs} power_chunk={pc} waves={w} changed the result")
+                results.append({"z_splits": zs, "power_chunk": pc, "waves": w, "ms": ms})
     best = min(results, key=lambda r: r["ms"])
-    set_tuning(shape, code, K, best["z_splits"], best["power_chunk"])
+    set_tuning(shape, code, K, best["z_splits"], best["power_chunk"], best["waves"])
     return {"key": _key(shape, code, K), "best": best, "candidates": results}
 
 
@@ -99,7 +103,7 @@ def save(results, path):
             table = json.load(fh)
     for r in results:
         table[r["key"]] = {"z_splits": r["best"]["z_splits"], "power_chunk": r["best"]["power_chunk"],
-                           "ms": r["best"]["ms"]}
+                           "waves": r["best"].get("waves", 0), "ms": r["best"]["ms"]}
     with open(path, "w") as fh:
         json.dump(table, fh, indent=1, sort_keys=True)
 
@@ -111,5 +115,5 @@ def load(path):
     for key, v in table.items():
         dims, code, K = key.split(":")
         L, M, N = (int(x) for x in dims.split("x"))
-        set_tuning((N, M, L), int(code), int(K), v["z_splits"], v["power_chunk"])
+        set_tuning((N, M, L), int(code), int(K), v["z_splits"], v["power_chunk"], v.get("waves", 0))
     return len(table)

@@ -197,6 +197,7 @@ struct Plan {
     int pow_passes = 0;  // column-tile passes of the matrix-core power kernel
     dpm_tuning tune{};   // override of this shape (dpm_tune_set), zero if none
     bool one_launch = false;  // orders 7-16: all direction groups in one projection launch
+    int waves = 4;            // waves per projection workgroup (first group, whole rows)
     int amax = 0;        // coordinate magnitudes covered by the power table
     RowLayout rl{};
     int nslots_used = 0;
@@ -358,6 +359,11 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
         if (best > 160 * 1024) return DPM_ERANGE;
     }
     p.one_launch = p.fast && p.ngroups > 1;
+    p.waves = (p.fast && p.tune.waves == 8) ? 8 : 4;
+    if (const char *e = std::getenv("DPM_SLICE_WAVES")) {
+        if (atoi(e) == 8 && p.fast) p.waves = 8;
+        if (atoi(e) == 4) p.waves = 4;
+    }
     if (const char *e = std::getenv("DPM_GROUP_LAUNCHES")) {
         if (atoi(e)) p.one_launch = false;
     }
@@ -493,6 +499,7 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
         a.rows = rows;
         a.rl = p.rl;
         a.images = images;
+        a.waves = p.waves;
         for (int i = 0; i < 7; ++i) {
             a.img_off[i] = (images && i < p.gnd[g]) ? img_off[group_begin(g) + i] : 0;
             a.img_w[i] = (images && i < p.gnd[g]) ? img_w[group_begin(g) + i] : 0;
@@ -617,6 +624,7 @@ int dpm_plan(const int64_t dims[3], dpm_dtype dtype, int max_order, dpm_plan_inf
     info->z_splits = p.zsplits;
     info->power_tiles = p.ntiles;
     info->power_chunk = p.rl.kchunk >= (1 << 30) ? 0 : p.rl.kchunk;
+    info->proj_waves = (p.fast && !p.chain) ? p.waves : 4;
     info->limbs_slice = p.nls;
     info->limbs_moment = p.nlr;
     info->bits_slice = p.bits_slice;
@@ -810,7 +818,9 @@ int dpm_tune_set(const int64_t dims[3], dpm_dtype dtype, int max_order, const dp
         g_tune.erase(key);
         return DPM_OK;
     }
-    if (t->z_splits < 0 || t->z_splits > 4096 || t->power_chunk < -1 || t->power_chunk > 4096) return DPM_EINVAL;
+    if (t->z_splits < 0 || t->z_splits > 4096 || t->power_chunk < -1 || t->power_chunk > 4096 ||
+        (t->waves != 0 && t->waves != 4 && t->waves != 8))
+        return DPM_EINVAL;
     g_tune[key] = *t;
     return DPM_OK;
 }

@@ -50,6 +50,7 @@ struct SliceArgs {
     int32_t *images;           // optional
     int64_t img_off[7];        // element offset of each image of the group
     int64_t img_w[7];          // widths
+    int32_t waves;             // first group, whole-row loads: 4 or 8 waves per workgroup
 };
 
 struct RoiDesc {

@@ -741,8 +741,10 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
 }
 
 // ------------------------------------------------------------ kernels
-template <typename VT, int D0, int ND, bool FAST, bool CHAIN = false>
-__global__ void __launch_bounds__((CHAIN ? CH_WAVES : slice_waves((int)sizeof(VT))) * 64)
+// NWV: waves per workgroup (4, or 8 for the first group's whole-row kernel when the
+// planner or the autotuner asks for it: few slices leave the CUs short of waves)
+template <typename VT, int D0, int ND, bool FAST, bool CHAIN = false, int NWV = 4>
+__global__ void __launch_bounds__((CHAIN ? CH_WAVES : NWV) * 64)
 slice_kernel(SliceArgs a) {
     extern __shared__ uint32_t lds[];
     __shared__ ItemGeom ig;
@@ -750,7 +752,7 @@ slice_kernel(SliceArgs a) {
     const int64_t y = item / a.zsplits;
     const int64_t zs = (item % a.zsplits) * a.zrows;
     const int64_t ze = zs + a.zrows < a.N ? zs + a.zrows : a.N;
-    slice_item<VT, D0, ND, FAST, CHAIN, CHAIN ? CH_WAVES : slice_waves((int)sizeof(VT))>(reinterpret_cast<const VT *>(a.vol), a.L, a.N, a.pitch_y, a.pitch_z, y, zs,
+    slice_item<VT, D0, ND, FAST, CHAIN, CHAIN ? CH_WAVES : NWV>(reinterpret_cast<const VT *>(a.vol), a.L, a.N, a.pitch_y, a.pitch_z, y, zs,
                                  ze, a.R, a.CT, a.rows + item * a.rl.row_stride, a.rl.slot_off,
                                  a.rl.slot_len, a.images, a.img_off, a.img_w, lds, ig);
 }
@@ -841,31 +843,31 @@ slice_batched_kernel(BatchSliceArgs a) {
 }
 
 // ------------------------------------------------------------ launch helpers
-template <typename VT, int D0, int ND, bool FAST, bool CHAIN = false>
+template <typename VT, int D0, int ND, bool FAST, bool CHAIN = false, int NWV = 4>
 hipError_t launch_one(const SliceArgs &a, int items, size_t lds, hipStream_t st) {
-    auto k = slice_kernel<VT, D0, ND, FAST, CHAIN>;
+    auto k = slice_kernel<VT, D0, ND, FAST, CHAIN, NWV>;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
         if (e != hipSuccess) return e;
     }
-    const int nw = CHAIN ? CH_WAVES : slice_waves((int)sizeof(VT));
+    const int nw = CHAIN ? CH_WAVES : NWV;
     hipLaunchKernelGGL(k, dim3(items), dim3(nw * 64), lds, st, a);
     return hipGetLastError();
 }
 
-template <typename VT, int D0, bool FAST, bool CHAIN = false>
+template <typename VT, int D0, bool FAST, bool CHAIN = false, int NWV = 4>
 hipError_t launch_nd(int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st) {
     switch (nd) {
-        case 1: return launch_one<VT, D0, 1, FAST, CHAIN>(a, items, lds, st);
-        case 2: return launch_one<VT, D0, 2, FAST, CHAIN>(a, items, lds, st);
-        case 3: return launch_one<VT, D0, 3, FAST, CHAIN>(a, items, lds, st);
-        case 4: return launch_one<VT, D0, 4, FAST, CHAIN>(a, items, lds, st);
-        case 5: return launch_one<VT, D0, 5, FAST, CHAIN>(a, items, lds, st);
+        case 1: return launch_one<VT, D0, 1, FAST, CHAIN, NWV>(a, items, lds, st);
+        case 2: return launch_one<VT, D0, 2, FAST, CHAIN, NWV>(a, items, lds, st);
+        case 3: return launch_one<VT, D0, 3, FAST, CHAIN, NWV>(a, items, lds, st);
+        case 4: return launch_one<VT, D0, 4, FAST, CHAIN, NWV>(a, items, lds, st);
+        case 5: return launch_one<VT, D0, 5, FAST, CHAIN, NWV>(a, items, lds, st);
         default:
             if constexpr (D0 == 0) {
-                if (nd == 6) return launch_one<VT, D0, 6, FAST, CHAIN>(a, items, lds, st);
-                if (nd == 7) return launch_one<VT, D0, 7, FAST, CHAIN>(a, items, lds, st);
+                if (nd == 6) return launch_one<VT, D0, 6, FAST, CHAIN, NWV>(a, items, lds, st);
+                if (nd == 7) return launch_one<VT, D0, 7, FAST, CHAIN, NWV>(a, items, lds, st);
             }
             return hipErrorInvalidValue;
     }

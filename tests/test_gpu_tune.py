@@ -23,8 +23,8 @@ def test_autotune_installs_an_exact_split():
     V = synth.uniform_volume((64, 48, 96), np.uint16, seed=2)
     vol = to_dev(V)
     try:
-        r = autotune.tune(vol, 6, reps=3, warmup=1, z_splits=(0, 1, 2, 4), power_chunks=(0, 4, -1))
-        assert len(r["candidates"]) == 12 and all(c["ms"] > 0 for c in r["candidates"])
+        r = autotune.tune(vol, 6, reps=3, warmup=1, z_splits=(0, 1, 2, 4), power_chunks=(0, 4, -1), waves=(0, 8))
+        assert len(r["candidates"]) == 24 and all(c["ms"] > 0 for c in r["candidates"])
         best = r["best"]
         info = dpm.plan(V.shape, 2, 6)
         if best["z_splits"]:

@@ -239,7 +239,15 @@ def test_tuning_overrides_change_the_plan_only(lib):
     assert lib.dpm_tune_set(d3(*dims), 2, 6, ctypes.byref(_lib.Tuning(2, 0))) == 0
     assert lib.dpm_tune_clear() == 0
     assert plan(lib, dims, 2, 6)[1].z_splits == base.z_splits
-    for bad in (_lib.Tuning(-1, 0), _lib.Tuning(5000, 0), _lib.Tuning(1, -2), _lib.Tuning(1, 5000)):
+    # waves per projection workgroup: whole-row shapes only
+    fast = (128, 64, 256)
+    assert plan(lib, fast, 2, 6)[1].proj_waves == 4
+    assert lib.dpm_tune_set(d3(*fast), 2, 6, ctypes.byref(_lib.Tuning(0, 0, 8))) == 0
+    assert plan(lib, fast, 2, 6)[1].proj_waves == 8
+    assert lib.dpm_tune_set(d3(*fast), 2, 6, None) == 0
+    assert plan(lib, fast, 2, 6)[1].proj_waves == 4
+    for bad in (_lib.Tuning(-1, 0), _lib.Tuning(5000, 0), _lib.Tuning(1, -2), _lib.Tuning(1, 5000),
+                _lib.Tuning(1, 0, 5)):
         assert lib.dpm_tune_set(d3(*dims), 2, 6, ctypes.byref(bad)) == -1
     assert lib.dpm_tune_set(d3(0, 4, 4), 2, 6, ctypes.byref(t)) == -1
     assert lib.dpm_tune_set(d3(*dims), 2, 17, ctypes.byref(t)) == -1
