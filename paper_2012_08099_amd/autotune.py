@@ -9,8 +9,10 @@ Three planner choices change how one volume's work is divided, never its result:
 * ``waves``: waves per projection workgroup (first direction group, whole-row loads): 8
   helps when there are too few slices to fill the CUs.
 
-``tune`` times every candidate triple with ``dpm_moments_async`` on one stream (HIP events
-around ``reps`` calls), requires each candidate's moments to be bit-identical to the
+``tune`` times every candidate triple with ``dpm_moments_async`` (HIP events around ``reps``
+calls: on one stream for the "latency" objective, alternating over two streams with a
+workspace each for the "throughput" objective, where one volume's power sums overlap the
+next one's projection), requires each candidate's moments to be bit-identical to the
 planner's default, installs the fastest with ``dpm_tune_set`` and returns the timings.
 Results can be kept in a JSON file (``save`` / ``load``) keyed by shape, dtype and order,
 and installed again in a later process without re-measuring.
@@ -48,7 +50,8 @@ def _key(shape, dtype_code, K):
     return f"{L}x{M}x{N}:{int(dtype_code)}:{int(K)}"
 
 
-def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS, waves=WAVES, stream=None):
+def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS, waves=WAVES, stream=None,
+         objective="latency"):
     """Measure every (z_splits, power_chunk, waves) candidate on the device volume ``vol``
     ((N, M, L) uint8, or uint16 carried as int16) and install the fastest.
 
@@ -61,25 +64,35 @@ def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS
     nm = num_moments(K)
     nm4 = num_moments(min(K, 4))
 
+    if objective not in ("latency", "throughput"):
+        raise ValueError("objective must be 'latency' or 'throughput'")
+    depth = 2 if objective == "throughput" else 1
+    streams = [st] + [torch.cuda.Stream(device=dev) for _ in range(depth - 1)]  # default priority
+
     def run(cand):
         if cand is None:
             unset_tuning(shape, code, K)
         else:
             set_tuning(shape, code, K, *cand)
-        ws = torch.empty(workspace_bytes(shape, code, K), dtype=torch.uint8, device=dev)
-        ex = torch.empty((nm4, 2), dtype=torch.int64, device=dev)
-        fp = torch.empty(nm, dtype=torch.float64, device=dev)
-        with torch.cuda.stream(st):
-            for _ in range(warmup):
-                moments_async(vol, K, ex, fp, ws, stream=st)
-            t0 = torch.cuda.Event(enable_timing=True)
-            t1 = torch.cuda.Event(enable_timing=True)
-            t0.record(st)
-            for _ in range(reps):
-                moments_async(vol, K, ex, fp, ws, stream=st)
-            t1.record(st)
+        nb = workspace_bytes(shape, code, K)
+        ws = [torch.empty(nb, dtype=torch.uint8, device=dev) for _ in range(depth)]
+        ex = [torch.empty((nm4, 2), dtype=torch.int64, device=dev) for _ in range(depth)]
+        fp = [torch.empty(nm, dtype=torch.float64, device=dev) for _ in range(depth)]
+        for i in range(warmup * depth):
+            moments_async(vol, K, ex[i % depth], fp[i % depth], ws[i % depth], stream=streams[i % depth])
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize(dev)
+        t0.record(st)
+        for s in streams[1:]:
+            s.wait_event(t0)
+        for i in range(reps):
+            moments_async(vol, K, ex[i % depth], fp[i % depth], ws[i % depth], stream=streams[i % depth])
+        for s in streams[1:]:
+            st.wait_stream(s)
+        t1.record(st)
         t1.synchronize()
-        return t0.elapsed_time(t1) / reps, ex.cpu(), fp.cpu()
+        return t0.elapsed_time(t1) / reps, ex[0].cpu(), fp[0].cpu()
 
     _, ref_ex, ref_fp = run(None)
     results = []
@@ -92,7 +105,7 @@ def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS
                 results.append({"z_splits": zs, "power_chunk": pc, "waves": w, "ms": ms})
     best = min(results, key=lambda r: r["ms"])
     set_tuning(shape, code, K, best["z_splits"], best["power_chunk"], best["waves"])
-    return {"key": _key(shape, code, K), "best": best, "candidates": results}
+    return {"key": _key(shape, code, K), "best": best, "candidates": results, "objective": objective}
 
 
 def save(results, path):

@@ -23,7 +23,8 @@ def test_autotune_installs_an_exact_split():
     V = synth.uniform_volume((64, 48, 96), np.uint16, seed=2)
     vol = to_dev(V)
     try:
-        r = autotune.tune(vol, 6, reps=3, warmup=1, z_splits=(0, 1, 2, 4), power_chunks=(0, 4, -1), waves=(0, 8))
+        r = autotune.tune(vol, 6, reps=3, warmup=1, z_splits=(0, 1, 2, 4), power_chunks=(0, 4, -1), waves=(0, 8),
+                          objective="throughput")
         assert len(r["candidates"]) == 24 and all(c["ms"] > 0 for c in r["candidates"])
         best = r["best"]
         info = dpm.plan(V.shape, 2, 6)
@@ -33,5 +34,8 @@ def test_autotune_installs_an_exact_split():
             assert info["power_chunk"] == best["power_chunk"]
         res = dpm.moments(vol, 6)
         assert_moments_equal(res, oracle.moments_exact(V, 6), 6, f"tuned {best}")
+        r2 = autotune.tune(vol, 6, reps=2, warmup=1, z_splits=(0, 2), power_chunks=(0,), waves=(0,))
+        assert r2["objective"] == "latency" and len(r2["candidates"]) == 2
+        assert_moments_equal(dpm.moments(vol, 6), oracle.moments_exact(V, 6), 6, f"tuned {r2['best']}")
     finally:
         autotune.clear()
