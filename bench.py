@@ -392,7 +392,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); the moments of one volume "
-              "need no collective, and multi-GPU runs are not part of this build", file=sys.stderr)
+              "need no collective, and this benchmark measures one GPU", file=sys.stderr)
         return 2
 
     if a.workload == "serve_mix":

@@ -1,5 +1,5 @@
 """bench.py's command-line contract, on the CPU: more than one GPU is refused with a
-message (the method needs no collective and this build measures one GPU), and the
+message (the moments of one volume need no collective; the bench measures one GPU), and the
 traffic counters are tied to the projection kernel's own sources."""
 import os
 import sys
