@@ -139,7 +139,8 @@ __device__ __forceinline__ void yweight_store(const PowerArgs &a, const TileInfo
 //    time through LDS;
 //  * split columns (power_mfma_cols_kernel), for more columns than one pass holds: wave w
 //    owns column tiles 4w .. 4w+3 for the whole contraction, so up to 16 column tiles take
-//    one pass, with plain LDS stores and one reassembly.
+//    one pass, with plain LDS stores and one reassembly; the waves take turns loading and
+//    limb-splitting the rows of a K-step and share the limbs through LDS.
 // Loads of PW_PF K-steps are in flight together; then every thread reassembles one
 // (item, k) sum.
 constexpr int PW_MW = 4;   // waves of the split-contraction kernel
@@ -149,6 +150,20 @@ constexpr int PW_SHORT = 512;  // rows up to this many values take the one-wave 
 constexpr int PW_CTILES = 4 * PW_NTP;  // column tiles of the split-columns kernel
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+
+// A_c = 7-bit limb c of 16 row values, four values per int32 (one byte each), the
+// byte order of the matrix cores' A operand.
+__device__ __forceinline__ void split_limbs(const uint32_t (&v)[16], v4i (&A)[4]) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            uint32_t w = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w |= ((v[4 * e + i] >> (7 * c)) & 0x7fu) << (8 * i);
+            A[c][e] = (int)w;
+        }
+}
 
 // Loads of PF K-steps: the 16 rows' values (A) and the limbs of a^k (B) of column tiles
 // t0 .. t0 + PW_NTP - 1; zero past ks_end or past the rows.
@@ -186,15 +201,7 @@ __device__ __forceinline__ void mma_steps(const StepBuf<PF> &b, int nt, int t0, 
                                 b.rq[f][2].x, b.rq[f][2].y, b.rq[f][2].z, b.rq[f][2].w,
                                 b.rq[f][3].x, b.rq[f][3].y, b.rq[f][3].z, b.rq[f][3].w};
         v4i A[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                uint32_t w = 0;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) w |= ((v[4 * e + i] >> (7 * c)) & 0x7fu) << (8 * i);
-                A[c][e] = (int)w;
-            }
+        split_limbs(v, A);
 #pragma unroll
         for (int tp = 0; tp < PW_NTP; ++tp) {
             if (t0 + tp < nt) {
@@ -309,7 +316,12 @@ __global__ void __launch_bounds__(MW * 64) power_mfma_kernel(PowerArgs a) {
 template <int NLS, int NLR>
 __global__ void __launch_bounds__(PW_MW * 64) power_mfma_cols_kernel(PowerArgs a) {
     constexpr int T = PW_MW * 64;
-    __shared__ int32_t ctab[4][PW_CTILES][256];
+    // LDS: during the contraction, the limb-split rows of PW_MW K-steps (two buffers,
+    // [buffer][step][limb][lane]); afterwards the limb-pair sums of every column tile
+    __shared__ int32_t lds[4 * PW_CTILES * 256];
+    static_assert(2 * PW_MW * 4 * 64 * 4 <= 4 * PW_CTILES * 256, "limb buffers exceed the LDS table");
+    int32_t(*ctab)[PW_CTILES][256] = reinterpret_cast<int32_t(*)[PW_CTILES][256]>(lds);
+    uint4 *abuf = reinterpret_cast<uint4 *>(lds);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     TileInfo ti;
     if (!decode_tile(a, blockIdx.x, ti)) return;  // uniform over the workgroup
@@ -325,7 +337,55 @@ __global__ void __launch_bounds__(PW_MW * 64) power_mfma_cols_kernel(PowerArgs a
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int tp = 0; tp < PW_NTP; ++tp) acc[c][tp] = v4i{0, 0, 0, 0};
-    if (t0 < nt) mfma_steps(rp, iv, bt, nt, t0, ti.ks0, ti.ks1, 1, acc);
+    // Every wave needs the limbs of the same rows at every K-step: wave w loads and splits
+    // step ks0 + w of each group of PW_MW steps and shares it through LDS, then every wave
+    // multiplies the group's steps into its own column tiles.  The loop bounds are uniform
+    // over the workgroup, so every wave reaches every barrier.
+    int buf = 0;
+    for (int ks0 = ti.ks0; ks0 < ti.ks1; ks0 += PW_MW, buf ^= 1) {
+        const int ks = ks0 + wave;
+        const bool oka = iv && ks < ti.ks1;
+        const uint4 *p = reinterpret_cast<const uint4 *>(rp + ks * 64);
+        uint4 rq[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) rq[i] = oka ? p[i] : make_uint4(0u, 0u, 0u, 0u);
+        uint4 bq[PW_MW][PW_NTP];
+#pragma unroll
+        for (int f = 0; f < PW_MW; ++f)
+#pragma unroll
+            for (int tp = 0; tp < PW_NTP; ++tp)
+                bq[f][tp] = (ks0 + f < ti.ks1 && t0 + tp < nt) ? bt[((size_t)(ks0 + f) * nt + t0 + tp) * 64]
+                                                               : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t v[16] = {rq[0].x, rq[0].y, rq[0].z, rq[0].w, rq[1].x, rq[1].y, rq[1].z, rq[1].w,
+                                rq[2].x, rq[2].y, rq[2].z, rq[2].w, rq[3].x, rq[3].y, rq[3].z, rq[3].w};
+        v4i A[4];
+        split_limbs(v, A);
+        uint4 *aw = abuf + (size_t)((buf * PW_MW + wave) * 4) * 64 + lane;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) __builtin_memcpy(&aw[c * 64], &A[c], 16);
+        // one barrier per group: a buffer is written again only two groups later, after
+        // every wave has passed the next group's barrier and so finished reading it
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < PW_MW; ++f) {
+            if (ks0 + f >= ti.ks1) break;
+            const uint4 *ar = abuf + (size_t)((buf * PW_MW + f) * 4) * 64 + lane;
+            v4i Af[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) __builtin_memcpy(&Af[c], &ar[c * 64], 16);
+#pragma unroll
+            for (int tp = 0; tp < PW_NTP; ++tp) {
+                if (t0 + tp < nt) {
+                    v4i B;
+                    __builtin_memcpy(&B, &bq[f][tp], 16);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[c][tp] = __builtin_amdgcn_mfma_i32_16x16x64_i8(Af[c], B, acc[c][tp], 0, 0, 0);
+                }
+            }
+        }
+    }
+    __syncthreads();  // the limb buffers share LDS with the sums table
     // every wave stores its own column tiles (tiles >= nt are never read)
 #pragma unroll
     for (int tp = 0; tp < PW_NTP; ++tp)
