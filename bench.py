@@ -428,7 +428,7 @@ def main(argv=None):
         from paper_2012_08099_amd import autotune
         t0 = time.perf_counter()
         r = autotune.tune(vols[0], K, reps=20, warmup=3, objective="throughput")
-        default = [c for c in r["candidates"] if c["z_splits"] == 0 and c["power_chunk"] == 0 and c["waves"] == 0][0]
+        default = [c for c in r["confirmed"] if c["z_splits"] == 0 and c["power_chunk"] == 0 and c["waves"] == 0][0]
         tuning = {"z_splits": r["best"]["z_splits"], "power_chunk": r["best"]["power_chunk"], "waves": r["best"]["waves"],
                   "ms_best": r["best"]["ms"], "ms_planner_default": default["ms"],
                   "candidates": len(r["candidates"]), "objective": r["objective"], "seconds": time.perf_counter() - t0}

@@ -51,11 +51,16 @@ def _key(shape, dtype_code, K):
 
 
 def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS, waves=WAVES, stream=None,
-         objective="latency"):
+         objective="latency", finalists=3, confirm_rounds=3):
     """Measure every (z_splits, power_chunk, waves) candidate on the device volume ``vol``
     ((N, M, L) uint8, or uint16 carried as int16) and install the fastest.
 
-    Returns {"best": {...}, "candidates": [{"z_splits", "power_chunk", "waves", "ms"}, ...]}."""
+    One sweep of short timings is noisy, so the ``finalists`` fastest candidates and the
+    planner's default (0, 0, 0) are timed again, ``confirm_rounds`` times each in turn with
+    twice the repetitions, and the one with the lowest median is installed.
+
+    Returns {"best": {...}, "candidates": [{"z_splits", "power_chunk", "waves", "ms"}, ...],
+    "confirmed": [{..., "ms": median of the confirmation rounds}, ...]}."""
     import torch
     code = _dtype_code(vol)
     shape = tuple(vol.shape)
@@ -69,7 +74,7 @@ def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS
     depth = 2 if objective == "throughput" else 1
     streams = [st] + [torch.cuda.Stream(device=dev) for _ in range(depth - 1)]  # default priority
 
-    def run(cand):
+    def run(cand, reps=reps):
         if cand is None:
             unset_tuning(shape, code, K)
         else:
@@ -103,9 +108,20 @@ def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS
                 if not (torch.equal(ex, ref_ex) and torch.equal(fp.view(torch.int64), ref_fp.view(torch.int64))):
                     raise RuntimeError(f"tuning candidate z_splits={zs} power_chunk={pc} waves={w} changed the result")
                 results.append({"z_splits": zs, "power_chunk": pc, "waves": w, "ms": ms})
-    best = min(results, key=lambda r: r["ms"])
+    trip = lambda r: (r["z_splits"], r["power_chunk"], r["waves"])
+    final = [trip(r) for r in sorted(results, key=lambda r: r["ms"])[:max(1, finalists)]]
+    if (0, 0, 0) not in final and any(trip(r) == (0, 0, 0) for r in results):
+        final.append((0, 0, 0))
+    times = {c: [] for c in final}
+    for _ in range(max(1, confirm_rounds)):
+        for c in final:
+            times[c].append(run(c, 2 * reps)[0])
+    confirmed = [{"z_splits": c[0], "power_chunk": c[1], "waves": c[2], "ms": sorted(t)[len(t) // 2]}
+                 for c, t in times.items()]
+    best = min(confirmed, key=lambda r: r["ms"])
     set_tuning(shape, code, K, best["z_splits"], best["power_chunk"], best["waves"])
-    return {"key": _key(shape, code, K), "best": best, "candidates": results, "objective": objective}
+    return {"key": _key(shape, code, K), "best": best, "candidates": results, "confirmed": confirmed,
+            "objective": objective}
 
 
 def save(results, path):
