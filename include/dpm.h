@@ -30,7 +30,8 @@
  *   - the library keeps no caller pointer after a call (async: after the stream work
  *     it enqueued has finished);
  *   - calls that enqueue on the same stream are ordered; calls on different streams
- *     must use different workspaces.
+ *     that pass their own workspace must pass different ones (calls that use the
+ *     library-owned workspace are ordered by the library, see dpm_moments_async).
  */
 #ifndef DPM_H
 #define DPM_H
@@ -99,8 +100,12 @@ int dpm_moments(const void *volume, const int64_t dims[3], dpm_dtype dtype, int 
                 dpm_out *out);
 
 /* Stream-ordered call.  volume, out_device->exact/fp64 and workspace are device
- * pointers; workspace must hold dpm_workspace_bytes() bytes (NULL = use the
- * library-owned workspace of this device, which serialises callers).  Returns after
+ * pointers; workspace must hold dpm_workspace_bytes() bytes, or be NULL to use the
+ * library-owned workspace of this device.  That workspace is shared by every call that
+ * brings none (dpm_moments, dpm_features, dpm_project_images, dpm_moments_from_images
+ * and this call with NULL): the library makes each such call's stream wait, on the
+ * device, for the work of the previous one (an event recorded after it), so calls on
+ * different streams never overlap on it -- they run one after another.  Returns after
  * enqueueing; results are valid once `stream` reaches this point.
  * Graph capture: with a caller workspace, and once an eager call of the same dims, dtype
  * and order has run on the device (it builds the device tables), the call enqueues

@@ -188,6 +188,8 @@ def project_images(vol, K, stream=None):
     widths = [image_width(vol.shape, d) for d in range(K + 1)]
     buf = torch.zeros(sum(w * M for w in widths), dtype=torch.int32, device=vol.device)
     st = stream if stream is not None else torch.cuda.current_stream(vol.device)
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream(vol.device))  # the zero fill above
     rc = lib().dpm_project_images(ctypes.c_void_p(vol.data_ptr()), _dims_of_shape(vol.shape), _dtype_code(vol),
                                   int(K), ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(st.cuda_stream))
     check(rc, "dpm_project_images")

@@ -44,11 +44,26 @@ def common_flags():
     ]
 
 
+def _includes(path, seen):
+    """The quoted #include files a source pulls in, recursively (csrc/ and include/)."""
+    import re
+    with open(path) as fh:
+        for line in fh:
+            m = re.match(r'\s*#include\s+"([^"]+)"', line)
+            if not m:
+                continue
+            dep = os.path.normpath(os.path.join(os.path.dirname(path), m.group(1)))
+            if dep not in seen and os.path.exists(dep):
+                seen.add(dep)
+                _includes(dep, seen)
+    return seen
+
+
 def _stale(src, obj):
     if not os.path.exists(obj):
         return True
-    deps = [os.path.join(CSRC, src)] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
-    deps.append(os.path.join(HERE, "..", "include", "dpm.h"))
+    path = os.path.join(CSRC, src)
+    deps = [path] + sorted(_includes(path, set()))
     t = os.path.getmtime(obj)
     return any(os.path.getmtime(d) > t for d in deps)
 

@@ -418,14 +418,6 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
 }
 
 // ------------------------------------------------------------------ workspaces
-struct DevWs {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-    void *out = nullptr;  // device staging for dpm_moments results
-    size_t out_bytes = 0;
-};
-DevWs g_ws[64];
-
 int ensure_buf(void *&ptr, size_t &have, size_t need) {
     if (have >= need && ptr) return DPM_OK;
     if (ptr) {
@@ -444,19 +436,77 @@ int ensure_buf(void *&ptr, size_t &have, size_t need) {
     return DPM_OK;
 }
 
+struct DevWs {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    void *out = nullptr;  // device staging for dpm_moments results
+    size_t out_bytes = 0;
+    hipEvent_t done = nullptr;  // recorded after the last work that used this workspace
+    bool used = false;
+};
+DevWs g_ws[64];
+
+// The library-owned workspace of a device is shared by every call that does not bring
+// its own.  Calls on different streams must not overlap on it: each user's stream first
+// waits for the event recorded after the previous user's work (ws_begin), and records it
+// again after its own (ws_end).  Both run under g_mu.
+int ws_begin(int dev, hipStream_t st) {
+    DevWs &w = g_ws[dev];
+    if (!w.done) {
+        hipError_t e = hipEventCreateWithFlags(&w.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            w.done = nullptr;
+            return hip_fail(e);
+        }
+    }
+    if (w.used) {
+        hipError_t e = hipStreamWaitEvent(st, w.done, 0);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return DPM_OK;
+}
+
+int ws_end(int dev, hipStream_t st) {
+    DevWs &w = g_ws[dev];
+    hipError_t e = hipEventRecord(w.done, st);
+    if (e != hipSuccess) return hip_fail(e);
+    w.used = true;
+    return DPM_OK;
+}
+
+// Grow a buffer of the shared workspace: the old one may still be read by work in
+// flight on another stream, so wait for that work before freeing it.
+int ensure_ws_buf(int dev, void *&ptr, size_t &have, size_t need) {
+    if (have >= need && ptr) return DPM_OK;
+    if (ptr && g_ws[dev].used) {
+        hipError_t e = hipEventSynchronize(g_ws[dev].done);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return ensure_buf(ptr, have, need);
+}
+
+
+// given_pow: a power table the caller built (the allocation-free entry point), else the
+// library's cached one; such calls record no stage events either.
 int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img_off,
              const int64_t *img_w, void *exact, double *fp64, void *ws, hipStream_t st,
-             uint32_t *raw = nullptr, const ImgArgs *from_images = nullptr) {
+             uint32_t *raw = nullptr, const ImgArgs *from_images = nullptr,
+             const PowTab *given_pow = nullptr) {
     uint8_t *base = static_cast<uint8_t *>(ws);
     int32_t *rows = reinterpret_cast<int32_t *>(base);
     uint32_t *part = reinterpret_cast<uint32_t *>(base + p.rows_bytes);
     PowTab pt{};
     const bool moments = (exact || fp64 || raw);
-    if (p.mfma && moments) {
+    if (given_pow) {
+        pt = *given_pow;
+    } else if (p.mfma && moments) {
         int prc = get_powtab(p.amax, p.K, pt);
         if (prc) return prc;
     }
-    if (moments) prof_mark(0, st);
+    auto mark = [&](int idx) {
+        if (!given_pow) prof_mark(idx, st);
+    };
+    if (moments) mark(0);
     if (from_images) {
         // step 1 replaced by supplied images: gather them into the row slots
         ImgArgs ia = *from_images;
@@ -519,10 +569,10 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
     for (int s = 0; s < NSLOT; ++s) pa.max_len = std::max(pa.max_len, p.rl.slot_len[s]);
     pa.pow = pt;
     pa.part = part;
-    prof_mark(1, st);
+    mark(1);
     hipError_t e = launch_power(p.nls, p.nlr, pa, st);
     if (e != hipSuccess) return hip_fail(e);
-    prof_mark(2, st);
+    mark(2);
     FinishArgs f{};
     f.part = part;
     f.rois = nullptr;
@@ -534,7 +584,7 @@ int run_plan(const Plan &p, const void *vol, int32_t *images, const int64_t *img
     f.raw = raw;
     e = launch_finish(p.nlr, f, st);
     if (e != hipSuccess) return hip_fail(e);
-    prof_mark(3, st);
+    mark(3);
     return DPM_OK;
 }
 
@@ -548,6 +598,41 @@ int current_device(int &dev) {
 }  // namespace
 
 namespace dpm {
+// The launch sequence of dpm_moments_async with every device buffer taken from one
+// caller-supplied region `scratch` (the allocation-free entry point): the power table of
+// the matrix-core power sums is built there by a kernel on `st` (first), followed by the
+// workspace.  Nothing is allocated.  *need = the bytes this request uses; DPM_ENOMEM if
+// they exceed scratch_bytes (nothing is enqueued then).
+int moments_in_scratch(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order,
+                       const dpm_out *out_device, uint8_t *scratch, size_t scratch_bytes, hipStream_t st,
+                       size_t *need) {
+    if (need) *need = 0;
+    if (!volume || !out_device || !scratch) return DPM_EINVAL;
+    if (int trc = ensure_device_tables()) return trc;
+    Plan p;
+    int rc = make_plan(dims, dtype, max_order, false, p, volume);
+    if (rc) return rc;
+    PowTab t{};
+    size_t tab_bytes = 0;
+    if (p.mfma) {
+        t.amax = (p.amax + 511) / 512 * 512;
+        if (!pow_columns(t.amax, p.K, t.colstart)) return DPM_ENOTSUP;
+        t.nt = (t.colstart[p.K + 1] + 15) / 16;
+        tab_bytes = align_up((size_t)(t.amax / 64) * t.nt * 64 * 16);
+    }
+    const size_t total = tab_bytes + p.ws_bytes;
+    if (need) *need = total;
+    if (total > scratch_bytes) return DPM_ENOMEM;
+    if (p.mfma) {
+        uint4 *tab = reinterpret_cast<uint4 *>(scratch);
+        hipError_t e = launch_powtab_build(tab, t, p.K, st);
+        if (e != hipSuccess) return hip_fail(e);
+        t.b = tab;
+    }
+    return run_plan(p, volume, nullptr, nullptr, nullptr, out_device->exact, out_device->fp64, scratch + tab_bytes,
+                    st, nullptr, nullptr, &t);
+}
+
 int batched_release();  // batched.cpp
 int batched_powtab(int amax, int K, PowTab &out) { return get_powtab(amax, K, out); }
 bool batched_pow_columns(int amax, int K, int32_t colstart[KMAX + 2]) { return pow_columns(amax, K, colstart); }
@@ -652,9 +737,12 @@ int dpm_moments_async(const void *volume, const int64_t dims[3], dpm_dtype dtype
     int dev;
     if ((rc = current_device(dev))) return rc;
     std::lock_guard<std::recursive_mutex> lk(g_mu);
-    if ((rc = ensure_buf(g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
-    return run_plan(p, volume, nullptr, nullptr, nullptr, out_device->exact, out_device->fp64,
-                    g_ws[dev].ptr, st);
+    if ((rc = ensure_ws_buf(dev, g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
+    if ((rc = ws_begin(dev, st))) return rc;
+    rc = run_plan(p, volume, nullptr, nullptr, nullptr, out_device->exact, out_device->fp64,
+                  g_ws[dev].ptr, st);
+    const int rc2 = ws_end(dev, st);
+    return rc ? rc : rc2;
 }
 
 int dpm_moments(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order,
@@ -669,13 +757,15 @@ int dpm_moments(const void *volume, const int64_t dims[3], dpm_dtype dtype, int 
     const int nm = n_moments(max_order), nm4 = n_moments(std::min(max_order, 4));
     const size_t ex_bytes = align_up((size_t)nm4 * 16), fp_bytes = align_up((size_t)nm * 8);
     std::lock_guard<std::recursive_mutex> lk(g_mu);
-    if ((rc = ensure_buf(g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
-    if ((rc = ensure_buf(g_ws[dev].out, g_ws[dev].out_bytes, ex_bytes + fp_bytes))) return rc;
+    if ((rc = ensure_ws_buf(dev, g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
+    if ((rc = ensure_ws_buf(dev, g_ws[dev].out, g_ws[dev].out_bytes, ex_bytes + fp_bytes))) return rc;
     uint8_t *ob = static_cast<uint8_t *>(g_ws[dev].out);
     void *dex = ob;
     double *dfp = reinterpret_cast<double *>(ob + ex_bytes);
+    if ((rc = ws_begin(dev, nullptr))) return rc;
     rc = run_plan(p, volume, nullptr, nullptr, nullptr, dex, dfp, g_ws[dev].ptr, nullptr);
-    if (rc) return rc;
+    const int rc2 = ws_end(dev, nullptr);
+    if (rc || rc2) return rc ? rc : rc2;
     hipError_t e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) return hip_fail(e);
     if (out->exact) {
@@ -712,13 +802,17 @@ int dpm_features(const void *volume, const int64_t dims[3], dpm_dtype dtype, int
     const int nm = n_moments(max_order);
     const size_t raw_bytes = align_up((size_t)n_moments(kr) * p.nlr * 4), d_bytes = align_up((size_t)(3 + 3 * nm) * 8);
     std::lock_guard<std::recursive_mutex> lk(g_mu);
-    if ((rc = ensure_buf(g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
-    if ((rc = ensure_buf(g_ws[dev].out, g_ws[dev].out_bytes, raw_bytes + d_bytes))) return rc;
+    if ((rc = ensure_ws_buf(dev, g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
+    if ((rc = ensure_ws_buf(dev, g_ws[dev].out, g_ws[dev].out_bytes, raw_bytes + d_bytes))) return rc;
     uint8_t *ob = static_cast<uint8_t *>(g_ws[dev].out);
     uint32_t *draw = reinterpret_cast<uint32_t *>(ob);
     double *dd = reinterpret_cast<double *>(ob + raw_bytes);
+    if ((rc = ws_begin(dev, nullptr))) return rc;
     rc = run_plan(p, volume, nullptr, nullptr, nullptr, nullptr, nullptr, g_ws[dev].ptr, nullptr, draw);
-    if (rc) return rc;
+    if (rc) {
+        (void)ws_end(dev, nullptr);
+        return rc;
+    }
     FeatArgs f{};
     f.raw = draw;
     f.K = max_order;
@@ -728,7 +822,9 @@ int dpm_features(const void *volume, const int64_t dims[3], dpm_dtype dtype, int
     f.eta = dd + 3 + nm;
     f.mu_phys = dd + 3 + 2 * nm;
     hipError_t e = launch_features(p.nlr, w, f, nullptr);
+    rc = ws_end(dev, nullptr);
     if (e != hipSuccess) return hip_fail(e);
+    if (rc) return rc;
     if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e);
     std::vector<double> h((size_t)3 + 3 * nm);
     if ((e = hipMemcpy(h.data(), dd, h.size() * 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e);
@@ -756,9 +852,12 @@ int dpm_project_images(const void *volume, const int64_t dims[3], dpm_dtype dtyp
     int dev;
     if ((rc = current_device(dev))) return rc;
     std::lock_guard<std::recursive_mutex> lk(g_mu);
-    if ((rc = ensure_buf(g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
-    return run_plan(p, volume, images_device, off, w, nullptr, nullptr, g_ws[dev].ptr,
-                    static_cast<hipStream_t>(stream));
+    if ((rc = ensure_ws_buf(dev, g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if ((rc = ws_begin(dev, st))) return rc;
+    rc = run_plan(p, volume, images_device, off, w, nullptr, nullptr, g_ws[dev].ptr, st);
+    const int rc2 = ws_end(dev, st);
+    return rc ? rc : rc2;
 }
 
 int dpm_moments_from_images(const int32_t *images_device, const int64_t dims[3], dpm_dtype dtype,
@@ -787,16 +886,21 @@ int dpm_moments_from_images(const int32_t *images_device, const int64_t dims[3],
     const int nm = n_moments(max_order), nm4 = n_moments(std::min(max_order, 4));
     const size_t ex_bytes = align_up((size_t)nm4 * 16), fp_bytes = align_up((size_t)nm * 8);
     std::lock_guard<std::recursive_mutex> lk(g_mu);
-    if ((rc = ensure_buf(g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
-    if ((rc = ensure_buf(g_ws[dev].out, g_ws[dev].out_bytes, ex_bytes + fp_bytes + 256))) return rc;
+    if ((rc = ensure_ws_buf(dev, g_ws[dev].ptr, g_ws[dev].bytes, p.ws_bytes))) return rc;
+    if ((rc = ensure_ws_buf(dev, g_ws[dev].out, g_ws[dev].out_bytes, ex_bytes + fp_bytes + 256))) return rc;
     uint8_t *ob = static_cast<uint8_t *>(g_ws[dev].out);
     void *dex = ob;
     double *dfp = reinterpret_cast<double *>(ob + ex_bytes);
     ia.bad = reinterpret_cast<uint32_t *>(ob + ex_bytes + fp_bytes);
+    if ((rc = ws_begin(dev, nullptr))) return rc;
     hipError_t e = hipMemsetAsync(ia.bad, 0, 4, nullptr);
-    if (e != hipSuccess) return hip_fail(e);
+    if (e != hipSuccess) {
+        (void)ws_end(dev, nullptr);
+        return hip_fail(e);
+    }
     rc = run_plan(p, nullptr, nullptr, nullptr, nullptr, dex, dfp, g_ws[dev].ptr, nullptr, nullptr, &ia);
-    if (rc) return rc;
+    const int rc2 = ws_end(dev, nullptr);
+    if (rc || rc2) return rc ? rc : rc2;
     uint32_t bad = 0;
     if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e);
     if ((e = hipMemcpy(&bad, ia.bad, 4, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(e);
@@ -842,10 +946,11 @@ int dpm_release(void) {
     }
     g_pow.clear();
     for (int d = 0; d < 64; ++d) {
-        if (!g_ws[d].ptr && !g_ws[d].out) continue;
+        if (!g_ws[d].ptr && !g_ws[d].out && !g_ws[d].done) continue;
         (void)hipSetDevice(d);
         if (g_ws[d].ptr && hipFree(g_ws[d].ptr) != hipSuccess) rc = DPM_EDEVICE;
         if (g_ws[d].out && hipFree(g_ws[d].out) != hipSuccess) rc = DPM_EDEVICE;
+        if (g_ws[d].done && hipEventDestroy(g_ws[d].done) != hipSuccess) rc = DPM_EDEVICE;
         g_ws[d] = DevWs{};
     }
     (void)hipSetDevice(cur);

@@ -101,6 +101,9 @@ struct PowerArgs {
     uint32_t *part;
 };
 hipError_t launch_power(int nls, int nlr, const PowerArgs &a, hipStream_t st);
+// Build the power table of `shape` (amax, nt, colstart; b ignored) into tab, which holds
+// amax / 64 * nt * 64 uint4, on the device: the same bytes as the host build.
+hipError_t launch_powtab_build(uint4 *tab, const PowTab &shape, int K, hipStream_t st);
 
 // chain: the chained-window variant (uint16, first group, whole 64-lane rows, z ranges
 // that are whole 32-row units)

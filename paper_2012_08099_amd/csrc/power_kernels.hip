@@ -480,6 +480,47 @@ static hipError_t power_go(const PowerArgs &a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// The power table of PowTab built on the device (same bytes as the host build): thread
+// (ks, tile, lane) writes the 16 limb bytes of column 16 tile + lane % 16 for
+// a = 64 ks + 16 (lane / 16) + i, i = 0..15; columns past colstart[K+1] are zero.
+__global__ void __launch_bounds__(256) powtab_build_kernel(uint4 *tab, int32_t nt, int32_t ncells, int32_t K,
+                                                          PowTab shape) {
+    const int cell = blockIdx.x * 256 + threadIdx.x;
+    if (cell >= ncells) return;
+    const int lane = cell % 64, tile = (cell / 64) % nt, ks = cell / (64 * nt);
+    const int col = tile * 16 + lane % 16, kq = lane / 16;
+    int k = -1;
+    for (int j = 0; j <= K; ++j)
+        if (col >= shape.colstart[j] && col < shape.colstart[j + 1]) k = j;
+    uint32_t bytes[4] = {0u, 0u, 0u, 0u};
+    if (k >= 0) {
+        const int bit = 7 * (col - shape.colstart[k]);
+        for (int i = 0; i < 16; ++i) {
+            const uint32_t a = (uint32_t)(64 * ks + 16 * kq + i);
+            mw::Int<8> v;
+            mw::set_u64(v, 1);
+            for (int j = 0; j < k; ++j) mw::mul_u32(v, a);
+            const int w0 = bit >> 5, sh = bit & 31;
+            uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+            for (int l = 0; l < 8; ++l) {
+                if (l == w0) lo = v.w[l] >> sh;
+                if (l == w0 + 1 && sh) hi = v.w[l] << (32 - sh);
+            }
+            bytes[i / 4] |= ((lo | hi) & 0x7fu) << (8 * (i % 4));
+        }
+    }
+    tab[cell] = make_uint4(bytes[0], bytes[1], bytes[2], bytes[3]);
+}
+
+hipError_t launch_powtab_build(uint4 *tab, const PowTab &shape, int K, hipStream_t st) {
+    const int ncells = shape.amax / 64 * shape.nt * 64;
+    if (ncells <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(powtab_build_kernel, dim3((ncells + 255) / 256), dim3(256), 0, st, tab, shape.nt, ncells, K,
+                       shape);
+    return hipGetLastError();
+}
+
 hipError_t launch_power(int nls, int nlr, const PowerArgs &a, hipStream_t st) {
     if (nls == 4 && nlr == 4) return power_go<4, 4>(a, st);
     if (nls == 4 && nlr == 8) return power_go<4, 8>(a, st);

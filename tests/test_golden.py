@@ -37,3 +37,44 @@ def test_golden_low_orders_independently(golden):
     assert ms[(1, 0, 0)] == int((V.sum(axis=(0, 1)) * x).sum())
     assert ms[(0, 1, 0)] == int((V.sum(axis=(0, 2)) * y).sum())
     assert ms[(0, 0, 1)] == int((V.sum(axis=(1, 2)) * z).sum())
+
+
+def test_golden_is_every_moment_to_order_16(golden):
+    assert len(golden["moments"]) == 969
+    assert sorted((p, q, r) for p, q, r, _ in golden["moments"]) == sorted(
+        (p, q, n - p - q) for n in range(17) for p in range(n + 1) for q in range(n - p + 1))
+
+
+def test_golden_moments_with_a_zero_index_from_the_marginals(golden):
+    """Every stored moment with p, q or r = 0 recomputed from the volume's 2D marginal sums
+    (eq. 2 summed over the missing axis first) with Python integers: a route that shares
+    nothing with the oracle's limb-split products."""
+    N, M, L = golden["volume"]["shape_zyx"]
+    V = synth.ct_phantom((N, M, L), seed=golden["volume"]["seed"]).astype(np.int64)
+    ms = {(p, q, r): int(v) for p, q, r, v in golden["moments"]}
+    K = golden["max_order"]
+    marg = {"xy": V.sum(axis=0), "xz": V.sum(axis=1), "yz": V.sum(axis=2)}  # [y][x], [z][x], [z][y]
+
+    def pw(n):
+        return np.array([[c ** k for k in range(K + 1)] for c in range(n)], dtype=object)
+
+    px, py, pz = pw(L), pw(M), pw(N)
+    # S[a][k] = sum_b marg[a][b] * b^k (inner axis first), then the outer powers
+    Sxy = marg["xy"].astype(object) @ px   # [y][p]
+    Sxz = marg["xz"].astype(object) @ px   # [z][p]
+    Syz = marg["yz"].astype(object) @ py   # [z][q]
+    Txy = py.T @ Sxy                       # [q][p]
+    Txz = pz.T @ Sxz                       # [r][p]
+    Tyz = pz.T @ Syz                       # [r][q]
+    n_checked = 0
+    for (p, q, r), v in ms.items():
+        if r == 0:
+            assert v == Txy[q][p], (p, q, r)
+        elif q == 0:
+            assert v == Txz[r][p], (p, q, r)
+        elif p == 0:
+            assert v == Tyz[r][q], (p, q, r)
+        else:
+            continue
+        n_checked += 1
+    assert n_checked == 969 - 560

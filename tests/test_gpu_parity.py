@@ -190,24 +190,6 @@ def test_ct_128_order16_full(dpm):
     assert_moments_equal(res, oracle.moments_exact(V, 16), 16, "ct128 K=16")
 
 
-def test_ct_512_order16_sampled_golden(dpm):
-    """The bench volume at order 16 (all three direction groups) against the stored,
-    oracle-computed sample of its moments (tests/golden)."""
-    import json
-    import os
-    say("ct 512^3 K=16 golden")
-    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ct512_k16_seed0.json")) as fh:
-        g = json.load(fh)
-    V = synth.ct_phantom(tuple(g["volume"]["shape_zyx"]), seed=g["volume"]["seed"])
-    res = dpm.moments(to_dev(V), 16)
-    for p, q, r, v in g["moments"]:
-        v = int(v)
-        i = dpm.moment_index(p, q, r)
-        assert res.fp64[i] == float(v), (p, q, r, res.fp64[i], v)
-        if p + q + r <= 4:
-            assert res.exact[i] == v, (p, q, r)
-
-
 def test_deterministic(dpm):
     V = synth.mri_phantom((64, 64, 64), seed=3)
     a = dpm.moments(to_dev(V), 9)

@@ -362,3 +362,57 @@ def test_features_order_zero_uses_first_order_raw_moments():
     assert f["mu"] == [float(raw[0])] and f["eta"] == [1.0]
     with pytest.raises(ValueError):
         oracle.central_from_raw(raw[:1], 0)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_features_mu_phys_is_the_physical_coordinate_sum(seed):
+    """Section 4's spacing normalisation pinned to what it stands for: the central moment
+    of the volume placed at physical positions (alpha x, beta y, delta z), every voxel
+    weighing its physical volume alpha beta delta -- a direct exact-rational sum over the
+    voxels, with anisotropic spacing."""
+    from fractions import Fraction
+    rng = np.random.default_rng(100 + seed)
+    V = rng.integers(0, 30, size=(4, 3, 5)).astype(np.uint8)
+    V[1, 1, 1] += 1
+    K = 4
+    spacing = (0.5, 0.75, 2.5)  # exactly representable
+    al, be, de = (Fraction(s) for s in spacing)
+    f = oracle.features(oracle.moments_exact(V, K), K, spacing=spacing)
+    zz, yy, xx = np.nonzero(V)
+    vals = [int(V[a, b, c]) for a, b, c in zip(zz, yy, xx)]
+    mass = sum(vals) * al * be * de
+    X = [al * int(c) for c in xx]
+    Y = [be * int(b) for b in yy]
+    Z = [de * int(a) for a in zz]
+    w = [v * al * be * de for v in vals]
+    xb = sum(wi * xi for wi, xi in zip(w, X)) / mass
+    yb = sum(wi * yi for wi, yi in zip(w, Y)) / mass
+    zb = sum(wi * zi for wi, zi in zip(w, Z)) / mass
+    for i, (p, q, r) in enumerate(oracle.moment_list(K)):
+        direct = sum(wi * (xi - xb) ** p * (yi - yb) ** q * (zi - zb) ** r for wi, xi, yi, zi in zip(w, X, Y, Z))
+        assert f["mu_phys"][i] == float(direct), (p, q, r)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_features_eta_exact_where_the_exponent_is_an_integer(seed):
+    """eta = mu / mu000^(n/3 + 1) is an exact rational when n/3 + 1 is an integer
+    (n = 0, 3, 6): there the oracle's value is the nearest double of mu / mu000^(n/3 + 1)
+    with mu the direct translated sum.  At every other order, eta^3 mu000^(n+3) = mu^3
+    (which fixes the exponent) to the working precision."""
+    from fractions import Fraction
+    rng = np.random.default_rng(200 + seed)
+    V = rng.integers(0, 12, size=(5, 4, 6)).astype(np.uint8)
+    V[2, 1, 3] += 1
+    K = 6
+    f = oracle.features(oracle.moments_exact(V, K), K)
+    mu = oracle.central_moments(V, K)
+    m000 = mu[(0, 0, 0)]
+    assert m000 == int(V.sum())
+    for i, (p, q, r) in enumerate(oracle.moment_list(K)):
+        n = p + q + r
+        if n % 3 == 0:
+            assert f["eta"][i] == float(mu[(p, q, r)] / Fraction(m000) ** (n // 3 + 1)), (p, q, r)
+        else:
+            lhs = Fraction(f["eta"][i]) ** 3 * Fraction(m000) ** (n + 3)
+            rhs = mu[(p, q, r)] ** 3
+            assert abs(lhs - rhs) <= Fraction(1, 10 ** 13) * abs(rhs) + Fraction(1, 10 ** 300), (p, q, r)
