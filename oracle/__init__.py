@@ -22,3 +22,11 @@ from .moments import (  # noqa: F401
     central_from_raw,
     features,
 )
+from .paper import (  # noqa: F401
+    DRT_DIRS,
+    drt_integrals,
+    moments_2d_from_integrals,
+    n_paper_images,
+    paper_images,
+    paper_moments,
+)
