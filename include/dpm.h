@@ -115,6 +115,28 @@ int dpm_moments_async(const void *volume, const int64_t dims[3], dpm_dtype dtype
                       int max_order, const dpm_out *out_device, void *workspace,
                       size_t ws_bytes, void *stream);
 
+/* ---- allocation-free variant of dpm_moments_async ------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, result and stream
+ * semantics as dpm_moments_async, but the workspace (and the power table of the
+ * matrix-core power sums, rebuilt by a kernel on `stream` at every call) live in a fixed
+ * device array of the library, DPM_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, held from the
+ * first call until the process ends.  The call allocates and frees nothing (the first
+ * call on a device also uploads the constant recombination tables, a copy).
+ * Every call on one GPU uses that GPU's single array: calls that overlap on one GPU
+ * (different streams, or threads) race and may return wrong results -- order them (one
+ * stream, or events).  Nothing in the array needs clearing: every byte the call reads it
+ * writes first.
+ * Errors: as dpm_moments_async; DPM_ENOMEM if the request needs more than the array
+ * (*scratch_needed, if not NULL, then holds the bytes it would need; e.g. 512^3 uint16
+ * needs about 16 MB at order 6 and fits up to order 15, while order 16 needs about
+ * 70 MiB: use dpm_moments_async with a caller workspace). */
+#define DPM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int dpm_moments_noalloc(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order,
+                        const dpm_out *out_device, void *stream, size_t *scratch_needed);
+/* DPM_NOALLOC_SCRATCH_BYTES, as built into the library. */
+size_t dpm_noalloc_scratch_bytes(void);
+
 /* The max_order+1 projection images of Section 3.1 (step 1 of the method), exact
  * int32.  images_device: device pointer to sum_d M * width_d int32 values; image d is
  * stored row-major as [y][i] right after image d-1.  For beta < 0 the column index

@@ -146,6 +146,22 @@ def moments_async(vol, K, out_exact, out_fp64, workspace, stream=None):
     check(rc, "dpm_moments_async")
 
 
+def moments_noalloc(vol, K, out_exact, out_fp64, stream=None):
+    """``moments_async`` without a workspace and without any allocation: the library's
+    fixed per-GPU scratch array holds the workspace (calls that overlap on one GPU race).
+    Returns the scratch bytes the request used."""
+    import torch
+    _check_volume(vol)
+    st = stream if stream is not None else torch.cuda.current_stream(vol.device)
+    out = Out(out_exact.data_ptr() if out_exact is not None else None,
+              out_fp64.data_ptr() if out_fp64 is not None else None)
+    need = ctypes.c_size_t(0)
+    rc = lib().dpm_moments_noalloc(ctypes.c_void_p(vol.data_ptr()), _dims_of_shape(vol.shape), _dtype_code(vol),
+                                   int(K), ctypes.byref(out), ctypes.c_void_p(st.cuda_stream), ctypes.byref(need))
+    check(rc, "dpm_moments_noalloc")
+    return int(need.value)
+
+
 def moments_from_images(images, shape, dtype_code, K):
     """Moments from the K+1 projection images of a (N, M, L) = ``shape`` volume (blocking).
     ``images``: one contiguous int32 device tensor in the layout of ``project_images``."""
