@@ -157,6 +157,50 @@ int dpm_project_images(const void *volume, const int64_t dims[3], dpm_dtype dtyp
 int dpm_moments_from_images(const int32_t *images_device, const int64_t dims[3], dpm_dtype dtype,
                             int max_order, dpm_out *out);
 
+/* ---- the paper's own route (orders <= 4) -----------------------------------------
+ * A verification mode that follows the paper literally.  Step 1 forms the five images
+ * of Section 3.1 from one pass over the volume:
+ *   XY  I(i = x, j = y)          eq. 5   M rows of L
+ *   YZ  I(i = y, j = z)          eq. 6   N rows of M
+ *   ZX  I(i = z, j = x)          eq. 7   L rows of N
+ *   X+Z I(i = x + z, j = y)      eq. 8   M rows of L + N - 1
+ *   X-Z I(i = x - z + N - 1, j = y)  eq. 9 (the column of the projection pseudo-code
+ *                                   of Section 5), M rows of L + N - 1
+ * -- the first three for orders <= 2, four for order 3, all five for order 4.  ZX sums
+ * over y while the others sum over z (or x), so no tile of the volume completes every
+ * image: each workgroup writes its partial images and a second kernel sums them in a
+ * fixed order (the default path's images avoid this; the difference is the extra
+ * traffic this mode exists to show).  Step 2 takes each image's 2D moments (eq. 1)
+ * from its five 1D integrals of Section 5 (onto the x and y axes, the 45 and 135 degree
+ * axes and the arctan(1/2) axis), by the binomial expansion of (a i + b j)^n.  Step 3
+ * is eqs. 10-16 -- eqs. 15 and 16 with their left-hand sides exchanged, as the
+ * expansion of (x +- z)^3 y requires -- after shifting the X-Z moments to the origin
+ * N - 1 (Section 5).  Results are exact: orders <= 4 as int128 and FP64 (nearest).
+ *
+ * dpm_paper_workspace_bytes: device workspace for a request (0 if invalid or outside
+ * the mode's range: max_order > 4, or an image's W + 2 (H - 1) >= 2^15, i.e. dims up to
+ * about 8191).  dpm_paper_images: the images only, into images_device (one after the
+ * other in the order above, each row-major [j][i], sum of W*H int32).
+ * dpm_moments_paper: the moments, stream-ordered, device outputs as dpm_moments_async.
+ * Errors: DPM_EINVAL (arguments), DPM_ENOTSUP (max_order > 4), DPM_ERANGE (range),
+ * DPM_ENOMEM (workspace smaller than dpm_paper_workspace_bytes). */
+size_t dpm_paper_workspace_bytes(const int64_t dims[3], dpm_dtype dtype, int max_order);
+int dpm_paper_images(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order,
+                     int32_t *images_device, void *workspace, size_t ws_bytes, void *stream);
+int dpm_moments_paper(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order,
+                      const dpm_out *out_device, void *workspace, size_t ws_bytes, void *stream);
+
+/* The default projection images (the family of dpm_project_images) with their 2D moments
+ * taken by the 1D-integral route of Section 5 instead of direct power sums (orders <= 4):
+ * each image's 1D integrals along (1,0), (0,1), (1,1), (1,-1), (1,2) in its (i, y) plane,
+ * their 1D moments about the image's origin, the exact 1D -> 2D inverse, then the
+ * recombination of Section 3.2 as in dpm_moments_async.  Same outputs and stream
+ * semantics as dpm_moments_async; workspace of dpm_drt_workspace_bytes (0 if invalid
+ * or out of range: orders > 4, or an image's width + 2 (M - 1) >= 2^15). */
+size_t dpm_drt_workspace_bytes(const int64_t dims[3], dpm_dtype dtype, int max_order);
+int dpm_moments_drt(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order,
+                    const dpm_out *out_device, void *workspace, size_t ws_bytes, void *stream);
+
 /* ---- object features (Section 4, after the moments) ---------------------------
  * From the exact moments of one volume (eq. 2), for every moment of order <= max_order
  * in graded order:

@@ -162,6 +162,105 @@ def moments_noalloc(vol, K, out_exact, out_fp64, stream=None):
     return int(need.value)
 
 
+def paper_workspace_bytes(shape, dtype_code, K):
+    """Workspace of the paper's own route (five images, 1D integrals, eqs. 10-16)."""
+    return int(lib().dpm_paper_workspace_bytes(_dims_of_shape(shape), int(dtype_code), int(K)))
+
+
+def _paper_ws(vol, K):
+    import torch
+    n = paper_workspace_bytes(vol.shape, _dtype_code(vol), K)
+    if n == 0:
+        check(-5 if K > 4 else -2, "dpm_paper_workspace_bytes")
+    return torch.empty(n, dtype=torch.uint8, device=vol.device)
+
+
+def paper_image_shapes(shape, K):
+    """(rows, columns) of the paper's images XY, YZ, ZX, X+Z, X-Z needed for order K."""
+    N, M, L = (int(s) for s in shape)
+    shapes = [(M, L), (N, M), (L, N), (M, L + N - 1), (M, L + N - 1)]
+    return shapes[:3 if K <= 2 else K + 1]
+
+
+def paper_images(vol, K, stream=None):
+    """The paper's images (XY, YZ, ZX, X+Z, X-Z as needed for order K) as int32 device
+    tensors img[j][i], formed by one pass over the volume."""
+    import torch
+    _check_volume(vol)
+    shapes = paper_image_shapes(vol.shape, K)
+    buf = torch.empty(sum(h * w for h, w in shapes), dtype=torch.int32, device=vol.device)
+    ws = _paper_ws(vol, K)
+    st = stream if stream is not None else torch.cuda.current_stream(vol.device)
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream(vol.device))
+    rc = lib().dpm_paper_images(ctypes.c_void_p(vol.data_ptr()), _dims_of_shape(vol.shape), _dtype_code(vol), int(K),
+                                ctypes.c_void_p(buf.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                ctypes.c_void_p(st.cuda_stream))
+    check(rc, "dpm_paper_images")
+    out, off = [], 0
+    for h, w in shapes:
+        out.append(buf[off:off + h * w].view(h, w))
+        off += h * w
+    st.synchronize()
+    return out
+
+
+def moments_paper_async(vol, K, out_exact, out_fp64, workspace, stream=None):
+    """The paper's route, enqueued on ``stream``; outputs and workspace are device tensors."""
+    import torch
+    _check_volume(vol)
+    st = stream if stream is not None else torch.cuda.current_stream(vol.device)
+    out = Out(out_exact.data_ptr() if out_exact is not None else None,
+              out_fp64.data_ptr() if out_fp64 is not None else None)
+    rc = lib().dpm_moments_paper(ctypes.c_void_p(vol.data_ptr()), _dims_of_shape(vol.shape), _dtype_code(vol), int(K),
+                                 ctypes.byref(out), ctypes.c_void_p(workspace.data_ptr()),
+                                 workspace.numel() * workspace.element_size(), ctypes.c_void_p(st.cuda_stream))
+    check(rc, "dpm_moments_paper")
+
+
+def moments_paper(vol, K):
+    """Moments of order <= K (<= 4) by the paper's route (blocking).  Returns ``Moments``."""
+    import torch
+    nm = num_moments(K)
+    ex = torch.empty((nm, 2), dtype=torch.int64, device=vol.device)
+    fp = torch.empty(nm, dtype=torch.float64, device=vol.device)
+    moments_paper_async(vol, K, ex, fp, _paper_ws(vol, K))
+    torch.cuda.current_stream(vol.device).synchronize()
+    return Moments(K, _exact_from_tensor(ex), fp.cpu().numpy())
+
+
+def drt_workspace_bytes(shape, dtype_code, K):
+    return int(lib().dpm_drt_workspace_bytes(_dims_of_shape(shape), int(dtype_code), int(K)))
+
+
+def moments_drt_async(vol, K, out_exact, out_fp64, workspace, stream=None):
+    """The default images with 2D moments by the 1D integrals of Section 5 (orders <= 4)."""
+    import torch
+    _check_volume(vol)
+    st = stream if stream is not None else torch.cuda.current_stream(vol.device)
+    out = Out(out_exact.data_ptr() if out_exact is not None else None,
+              out_fp64.data_ptr() if out_fp64 is not None else None)
+    rc = lib().dpm_moments_drt(ctypes.c_void_p(vol.data_ptr()), _dims_of_shape(vol.shape), _dtype_code(vol), int(K),
+                               ctypes.byref(out), ctypes.c_void_p(workspace.data_ptr()),
+                               workspace.numel() * workspace.element_size(), ctypes.c_void_p(st.cuda_stream))
+    check(rc, "dpm_moments_drt")
+
+
+def moments_drt(vol, K):
+    import torch
+    _check_volume(vol)
+    n = drt_workspace_bytes(vol.shape, _dtype_code(vol), K)
+    if n == 0:
+        check(-5 if K > 4 else -2, "dpm_drt_workspace_bytes")
+    ws = torch.empty(n, dtype=torch.uint8, device=vol.device)
+    nm, nm4 = num_moments(K), num_moments(min(K, 4))
+    ex = torch.empty((nm4, 2), dtype=torch.int64, device=vol.device)
+    fp = torch.empty(nm, dtype=torch.float64, device=vol.device)
+    moments_drt_async(vol, K, ex, fp, ws)
+    torch.cuda.current_stream(vol.device).synchronize()
+    return Moments(K, _exact_from_tensor(ex), fp.cpu().numpy())
+
+
 def moments_from_images(images, shape, dtype_code, K):
     """Moments from the K+1 projection images of a (N, M, L) = ``shape`` volume (blocking).
     ``images``: one contiguous int32 device tensor in the layout of ``project_images``."""

@@ -112,6 +112,14 @@ SIGNATURES = {
                                            ctypes.c_int, ctypes.POINTER(Out), ctypes.c_void_p,
                                            ctypes.POINTER(ctypes.c_size_t)]),
     "dpm_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "dpm_paper_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int]),
+    "dpm_paper_images": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dpm_moments_paper": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(Out), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dpm_drt_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int]),
+    "dpm_moments_drt": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                       ctypes.POINTER(Out), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "dpm_project_images": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
                                           ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "dpm_batched_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Roi), ctypes.c_int, ctypes.c_int]),

@@ -633,6 +633,28 @@ int moments_in_scratch(const void *volume, const int64_t dims[3], dpm_dtype dtyp
                     st, nullptr, nullptr, &t);
 }
 
+// The K+1 projection images of the family (the layout of dpm_project_images) into
+// `images`, with the projection's own rows/partials in `ws`; used by the 1D-integral
+// route.  *ws_need = the bytes ws must hold (query with images == null).
+int family_images(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order, int32_t *images,
+                  void *ws, size_t ws_bytes, hipStream_t st, size_t *ws_need) {
+    if (int trc = ensure_device_tables()) return trc;
+    Plan p;
+    int rc = make_plan(dims, dtype, max_order, true, p, volume);
+    if (rc) return rc;
+    if (ws_need) *ws_need = p.ws_bytes;
+    if (!images) return DPM_OK;
+    if (!volume || !ws || ws_bytes < p.ws_bytes) return DPM_EINVAL;
+    int64_t off[NDIR_MAX], w[NDIR_MAX];
+    int64_t acc = 0;
+    for (int d = 0; d < p.nd; ++d) {
+        w[d] = dpm_image_width(dims, d);
+        off[d] = acc;
+        acc += w[d] * p.M;
+    }
+    return run_plan(p, volume, images, off, w, nullptr, nullptr, ws, st);
+}
+
 int batched_release();  // batched.cpp
 int batched_powtab(int amax, int K, PowTab &out) { return get_powtab(amax, K, out); }
 bool batched_pow_columns(int amax, int K, int32_t colstart[KMAX + 2]) { return pow_columns(amax, K, colstart); }
