@@ -80,29 +80,53 @@ def to_dev(V):
     return t.to("cuda:0")
 
 
-def cpu_baseline(V, K, target_s=12.0):
-    """The naive direct-sum oracle (eq. 2 per voxel, every monomial) on a bounded sample:
-    z-slabs of volume 0, then whole passes over it, until about target_s of CPU time."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(V, K, target_s=4.0, runs=3):
+    """The oracle on the host cores, on bounded samples of volume 0:
+    - the naive direct sum (oracle/naive.c: eq. 2 per voxel, every monomial, int128,
+      OpenMP over all cores): a z-slab sized for about target_s, timed `runs` times,
+      the median reported (voxels/s);
+    - the exact Python oracle (oracle.moments_exact: eq. 2 with hoisted powers, exact
+      integers; one process): the whole of volume 0, timed once."""
+    import statistics
+
+    import oracle
     import oracle.native as onative
     onative.build(force=False)
     nz = 4
     t0 = time.perf_counter()
     onative.moments_direct(V[:nz], K)
-    rate = nz / max(time.perf_counter() - t0, 1e-3)  # z-rows per second
+    rate = nz / max(time.perf_counter() - t0, 1e-3)  # z-planes per second
     nz = int(min(V.shape[0], max(4, rate * target_s)))
-    vox, passes = 0, 0
-    t0 = time.perf_counter()
-    while True:
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
         onative.moments_direct(V[:nz], K)
-        vox += nz * V.shape[1] * V.shape[2]
-        passes += 1
-        if time.perf_counter() - t0 >= target_s or nz < V.shape[0]:
-            break
-    dt = time.perf_counter() - t0
-    what = f"{passes} pass(es) over all of volume 0" if nz == V.shape[0] else f"z-slab {nz}x{V.shape[1]}x{V.shape[2]} of volume 0"
-    return {"value": vox / dt, "unit": "voxels/s", "cores": onative.num_threads(), "kind": "oracle",
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    vox = nz * V.shape[1] * V.shape[2]
+    pz = V.shape[0]
+    t0 = time.perf_counter()
+    oracle.moments_exact(V[:pz], K)
+    py_s = time.perf_counter() - t0
+    py_vox = pz * V.shape[1] * V.shape[2]
+    return {"value": vox / med, "unit": "voxels/s", "cores": onative.num_threads(), "kind": "oracle",
             "sample": f"direct per-voxel sum of eq. (2), all {(K + 1) * (K + 2) * (K + 3) // 6} monomials, "
-                      f"exact int128, {what} ({dt:.1f} s)"}
+                      f"exact int128, z-slab {nz}x{V.shape[1]}x{V.shape[2]} of volume 0, median of {runs} runs",
+            "runs_s": times, "cpu_model": cpu_model(),
+            "python_oracle": {"value": py_vox / py_s, "unit": "voxels/s", "threads": 1, "seconds": py_s,
+                              "sample": f"oracle.moments_exact (eq. 2, hoisted powers, exact integers) on all "
+                                        f"{pz}x{V.shape[1]}x{V.shape[2]} of volume 0"}}
 
 
 # The paper's Table 1: DPM times (ms) on an Intel Core i5 (7th generation) for 1-byte
@@ -179,15 +203,16 @@ def read_traffic(workload, shash):
     return t.get("bytes_per_launch")
 
 
-def serve_main(a):
+def serve_leg(a, requests, modes=("device", "host"), ct0=None, log_prefix="serve"):
     """Served workload: a Poisson stream of mixed requests through dpm_server.
 
     Mix (per request): 70% uint8 sphere-mask ROIs with dims U{32..128}^3, 25% uint16
     MRI-like 256x256xZ with Z in [100, 300], 5% 512^3 uint16 CT-like; K = 6.  Volumes
     come from pools of pre-generated inputs (64 / 8 / 3 distinct).  First the capacity
-    (all requests arriving at once), then Poisson arrivals at 0.5x and 0.8x of it; each
-    with the inputs resident on the device and in pinned host memory (copied per
-    request).  Latency = result in the caller's buffer - scheduled arrival.
+    (all requests arriving at once), then Poisson arrivals at 0.5x and 0.8x of it; per
+    mode: inputs resident on the device, or in pinned host memory (copied per request).
+    Latency = result in the caller's buffer - scheduled arrival.  Beside them, the plain
+    path: the same requests one dpm_moments_async call after another on one stream.
     """
     import numpy as np
     import threading
@@ -201,15 +226,16 @@ def serve_main(a):
     t0 = time.perf_counter()
     small = [synth.sphere_mask(tuple(int(v) for v in rng.integers(32, 129, size=3)), rng) for _ in range(64)]
     mid = [synth.mri_phantom((int(rng.integers(100, 301)), 256, 256), seed=s) for s in range(8)]
-    ct0 = make_volume("ct", (512, 512, 512), "u16", 0)
-    log(f"pools generated in {time.perf_counter() - t0:.1f} s")
+    if ct0 is None:
+        ct0 = make_volume("ct", (512, 512, 512), "u16", 0)
+    log(f"{log_prefix}: pools generated in {time.perf_counter() - t0:.1f} s")
 
     def to_t(V, dev):
         t = torch.from_numpy(V.view(np.int16) if V.dtype == np.uint16 else V)
         return t.to("cuda:0") if dev else t.pin_memory()
 
     results = {}
-    for mode in ("device", "host"):
+    for mode in modes:
         dev = mode == "device"
         ps = [to_t(V, dev) for V in small]
         pm = [to_t(V, dev) for V in mid]
@@ -217,7 +243,8 @@ def serve_main(a):
         pc = [c0, torch.flip(c0, dims=[2]).contiguous(), torch.roll(c0, shifts=37, dims=0).contiguous()]
         if not dev:
             pc = [t.pin_memory() if not t.is_pinned() else t for t in pc]
-        kinds = rng.choice(3, size=a.requests, p=[0.70, 0.25, 0.05])
+        torch.cuda.synchronize()  # the pools are complete before any request reads them
+        kinds = rng.choice(3, size=requests, p=[0.70, 0.25, 0.05])
         vols = [ps[int(rng.integers(len(ps)))] if k == 0 else pm[int(rng.integers(len(pm)))] if k == 1
                 else pc[int(rng.integers(len(pc)))] for k in kinds]
         nvox = sum(int(v.numel()) for v in vols)
@@ -268,17 +295,18 @@ def serve_main(a):
                     "p99_ms_single": float(np.percentile(lat[~bat], 99)) if (~bat).any() else None}
 
         cap = run(0.0)
-        log(mode, "capacity", cap)
+        log(log_prefix, mode, "capacity", cap)
         r50 = run(0.5 * cap["served_per_s"])
-        log(mode, "0.5x", r50)
+        log(log_prefix, mode, "0.5x", r50)
         r80 = run(0.8 * cap["served_per_s"])
-        log(mode, "0.8x", r80)
-        # plain path for reference: one request after another on one stream
-        ws_b = max(dpm.workspace_bytes(tuple(v.shape), 2 if v.dtype == torch.int16 else 1, K) for v in vols[:200])
+        log(log_prefix, mode, "0.8x", r80)
+        # plain path for reference: the same requests one after another on one stream
+        nplain = min(len(vols), 500)
+        ws_b = max(dpm.workspace_bytes(tuple(v.shape), 2 if v.dtype == torch.int16 else 1, K) for v in vols[:nplain])
         ws = torch.empty(ws_b, dtype=torch.uint8, device="cuda:0")
         ex = torch.empty((35, 2), dtype=torch.int64, device="cuda:0")
         fp = torch.empty(84, dtype=torch.float64, device="cuda:0")
-        plain = vols[:200] if dev else [v.to("cuda:0", non_blocking=True) for v in vols[:200]]
+        plain = vols[:nplain] if dev else [v.to("cuda:0", non_blocking=True) for v in vols[:nplain]]
         torch.cuda.synchronize()
         tp = time.perf_counter()
         for v in plain:
@@ -286,10 +314,16 @@ def serve_main(a):
         torch.cuda.synchronize()
         plain_s = (time.perf_counter() - tp) / len(plain)
         results[mode] = {"capacity": cap, "poisson_0.5x": r50, "poisson_0.8x": r80,
-                         "plain_serial_per_s": 1.0 / plain_s}
+                         "plain_serial_per_s": 1.0 / plain_s, "plain_requests_timed": nplain,
+                         "voxels_per_request_mean": nvox / len(vols)}
         del ps, pm, pc, vols, plain
         torch.cuda.empty_cache()
+    return results
 
+
+def serve_main(a):
+    """The served workload on its own (both input modes, --requests per run)."""
+    results = serve_leg(a, a.requests)
     out = {"metric": "served requests/s (mix 70% u8 ROI 32-128^3 / 25% u16 256x256xZ / 5% 512^3 u16, K=6)",
            "value": results["device"]["capacity"]["served_per_s"], "unit": "requests/s", "n_gpus": 1,
            "higher_is_better": True, "data": "synthetic", "requests": a.requests,
@@ -299,11 +333,11 @@ def serve_main(a):
     return 0
 
 
-def rois_main(a):
-    """Batched ROIs: 1000 uint8 sphere-mask ROIs with dims U{8..96}^3 (sizes vary per
-    axis), K = 4 (35 exact moments each), all packed in one device buffer.  One step =
-    every ROI's moments by one dpm_moments_batched launch sequence; compared with the
-    same ROIs as 1000 plain dpm_moments_async calls on one stream."""
+def rois_leg(n, seed, steps, warmup):
+    """Batched ROIs: n uint8 sphere-mask ROIs with dims U{8..96}^3 (sizes vary per axis),
+    K = 4 (35 exact moments each), all packed in one device buffer.  One step = every
+    ROI's moments by one dpm_moments_batched launch sequence; compared with the same ROIs
+    as n plain dpm_moments_async calls on one stream."""
     import numpy as np
     import torch
 
@@ -312,7 +346,7 @@ def rois_main(a):
 
     K = 4
     t0 = time.perf_counter()
-    vols = synth.roi_batch(n=a.requests, seed=a.seed)
+    vols = synth.roi_batch(n=n, seed=seed)
     log(f"{len(vols)} ROIs generated in {time.perf_counter() - t0:.1f} s")
     packed, rois = dpm.pack_rois(vols, "cuda:0")
     n = len(vols)
@@ -333,12 +367,12 @@ def rois_main(a):
         return e0.elapsed_time(e1) / steps
 
     batched = lambda: dpm.moments_batched(packed, rois, K, ex, fp, ws)  # noqa: E731
-    for _ in range(a.warmup):
+    for _ in range(warmup):
         batched()
-    ms_b = timed(batched, a.steps)
+    ms_b = timed(batched, steps)
     dpm.profile_collect()
     dpm.profile_enable(True)
-    for _ in range(a.steps):
+    for _ in range(steps):
         batched()
     torch.cuda.synchronize()
     dpm.profile_enable(False)
@@ -355,17 +389,89 @@ def rois_main(a):
         for v in singles:
             dpm.moments_async(v, K, ex1, fp1, ws1)
     plain()
-    ms_p = timed(plain, max(1, a.steps // 10))
+    ms_p = timed(plain, max(1, steps // 10))
     # the batched results equal single calls (spot check a few ROIs)
     for i in (0, n // 2, n - 1):
         r = dpm.moments(singles[i], K)
         assert r.exact == [dpm.i128_to_int(int(lo) & (2 ** 64 - 1), int(hi)) for lo, hi in ex[i].tolist()]
+    return {"rois": n, "voxels": nvox, "ms_per_batch": ms_b, "rois_per_s": n / (ms_b / 1e3),
+            "voxels_per_s": nvox / (ms_b / 1e3), "hbm_frac_algorithmic": nvox / (ms_b / 1e3) / (HBM_PEAK_GBS * 1e9),
+            "plain_launches_ms": ms_p, "speedup_vs_plain": ms_p / ms_b, "stages_ms": stages,
+            "workspace_bytes": int(ws.numel())}
+
+
+def rois_main(a):
+    r = rois_leg(a.requests, a.seed, a.steps, a.warmup)
+    n, nvox, ms_b = r["rois"], r["voxels"], r["ms_per_batch"]
     out = {"metric": "ROIs/s (1000 u8 ROIs U{8..96}^3, orders <= 4)", "value": n / (ms_b / 1e3), "unit": "ROIs/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_b, "higher_is_better": True,
            "dtype": "u8", "data": "synthetic",
            "config": {"workload": f"rois{n}: {n} uint8 sphere-mask ROIs, dims U{{8..96}}^3, {nvox} voxels, K=4"},
-           "voxels_per_s": nvox / (ms_b / 1e3),
-           "plain_launches_ms": ms_p, "speedup_vs_plain": ms_p / ms_b, "stages_ms": stages}
+           "voxels_per_s": r["voxels_per_s"], "plain_launches_ms": r["plain_launches_ms"],
+           "speedup_vs_plain": r["speedup_vs_plain"], "stages_ms": r["stages_ms"]}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def paper_leg(vols, shape, code, K=4, reps=10):
+    """The paper's own route (five images incl. ZX with partial images summed in a fixed
+    order, 1D integrals, eqs. 10-16) and the 1D-integral route for the default images,
+    timed per call (HIP events, one stream, volumes rotated) beside the default path at
+    the same order; with the paper route's extra bytes (partial images written and read
+    back) from its workspace layout."""
+    import torch
+
+    import paper_2012_08099_amd as dpm
+    nm = dpm.num_moments(K)
+    ex = torch.empty((nm, 2), dtype=torch.int64, device="cuda:0")
+    fp = torch.empty(nm, dtype=torch.float64, device="cuda:0")
+    ws_p = torch.empty(dpm.paper_workspace_bytes(shape, code, K), dtype=torch.uint8, device="cuda:0")
+    ws_d = torch.empty(dpm.drt_workspace_bytes(shape, code, K), dtype=torch.uint8, device="cuda:0")
+    ws_f = torch.empty(dpm.workspace_bytes(shape, code, K), dtype=torch.uint8, device="cuda:0")
+    calls = {"default": lambda v: dpm.moments_async(v, K, ex, fp, ws_f),
+             "paper": lambda v: dpm.moments_paper_async(v, K, ex, fp, ws_p),
+             "drt": lambda v: dpm.moments_drt_async(v, K, ex, fp, ws_d)}
+    res = {}
+    ref = None
+    for name, fn in calls.items():
+        for i in range(3):
+            fn(vols[i % len(vols)])
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(reps):
+            fn(vols[i % len(vols)])
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = e0.elapsed_time(e1) / reps
+        got = dpm._exact_from_tensor(ex)
+        if ref is None:
+            ref = got
+        assert got == ref, f"{name} route differs from the default path"
+    N, M, L = shape
+    elem = 1 if code == 1 else 2
+    PP_BY, PP_BZ, PP_XT, PP_DW = 16, 64, 512, 512 + 64 - 1
+    nyb, nzb, nxt = -(-M // PP_BY), -(-N // PP_BZ), -(-L // PP_XT)
+    ndiag = (K >= 3) + (K >= 4)  # X+Z from order 3, X-Z at order 4
+    part = 4 * (nzb * M * L + ndiag * nzb * nxt * M * PP_DW + nyb * N * L + nxt * N * M)
+    res.update({"order": K, "volume_bytes": N * M * L * elem, "paper_partial_bytes_written": part,
+                "paper_extra_traffic_frac": 2 * part / (N * M * L * elem),
+                "paper_vs_default": res["paper_ms"] / res["default_ms"],
+                "drt_vs_default": res["drt_ms"] / res["default_ms"]})
+    return res
+
+
+def paper_main(a):
+    """The paper's own route and the 1D-integral route at order 4 on the 512^3 uint16
+    CT-like volume (three rotated copies), beside the default path."""
+    import torch
+    V0 = make_volume("ct", (512, 512, 512), "u16", 0)
+    v0 = to_dev(V0)
+    vols = [v0, torch.flip(v0, dims=[2]).contiguous(), torch.roll(v0, shifts=37, dims=0).contiguous()]
+    r = paper_leg(vols, (512, 512, 512), 2, K=4, reps=a.steps)
+    out = {"metric": "ms per 512^3 uint16 volume, orders <= 4, the paper's own route", "value": r["paper_ms"],
+           "unit": "ms", "n_gpus": 1, "steps": a.steps, "higher_is_better": False, "dtype": "u16",
+           "data": "synthetic", "config": {"workload": "paper_route: 512x512x512 u16 CT-like phantom, K=4"}, **r}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -376,7 +482,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="ct512_k6",
-                    choices=sorted(WORKLOADS) + ["serve_mix", "rois1000", "table1_sweep"])
+                    choices=sorted(WORKLOADS) + ["serve_mix", "rois1000", "table1_sweep", "paper_route"])
     ap.add_argument("--requests", type=int, default=10000, help="serve_mix: requests per run; rois1000: ROIs")
     ap.add_argument("--hbm-budget", type=int, default=16, help="serve_mix: server arena, GiB")
     ap.add_argument("--server-streams", type=int, default=4, help="serve_mix: server streams")
@@ -387,6 +493,9 @@ def main(argv=None):
     ap.add_argument("--streams", type=int, default=2,
                     help="volumes in flight (one stream and workspace each)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the short batched / served / paper-route legs of the default run")
+    ap.add_argument("--serve-requests", type=int, default=3000, help="requests per run of the served leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (planner defaults for the work split)")
     a = ap.parse_args(argv)
@@ -399,6 +508,8 @@ def main(argv=None):
         return serve_main(a)
     if a.workload == "table1_sweep":
         return sweep_main(a)
+    if a.workload == "paper_route":
+        return paper_main(a)
     if a.workload == "rois1000":
         if a.requests == 10000:
             a.requests = 1000
@@ -497,6 +608,8 @@ def main(argv=None):
     prof = dpm.profile_collect()
 
     proj_ms = prof["ms_project"] / max(prof["calls"], 1)
+    proj_kernel = ("slice_kernel (projection, one pass over the volume)" if plan["n_groups"] == 1 else
+                   "slice_groups_kernel (projection, one pass over the volume, all direction groups)")
     bytes_launch = voxels * elem
     achieved = bytes_launch / (proj_ms / 1e3) / 1e9
     shash = source_hash()
@@ -529,14 +642,31 @@ def main(argv=None):
                       "total_with_events": prof["ms_total"] / max(prof["calls"], 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "slice_kernel (projection, one pass over the volume)",
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "kernel": proj_kernel,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     # the whole kernel sequence of a step (projection, power sums,
+                     # recombination) against the same bytes: per step of the headline
+                     # (2 streams) and per volume on one stream
+                     "sequence_frac": bytes_launch / (ms_step / 1e3) / (HBM_PEAK_GBS * 1e9),
+                     "sequence_frac_single_stream": bytes_launch / (ms_serial / 1e3) / (HBM_PEAK_GBS * 1e9)},
         "source_hash": shash,
         "tuning": tuning,
         "features": {"call_ms_blocking": features_ms, "centroid": [float(c) for c in feats["centroid"]]},
         "from_images": {"call_ms_blocking": from_images_ms},
         "plan": {k: plan[k] for k in ("z_splits", "n_items", "power_tiles", "power_chunk", "proj_waves")},
     }
+    if not a.no_legs:
+        # the other workloads, short: batched ROIs, the served mix (device inputs), and
+        # the paper's own route / the 1D-integral route at order 4 on this volume
+        if K <= 6:
+            out["paper_route"] = paper_leg(vols, shape, code, K=4)
+            log("paper_route", out["paper_route"])
+        out["rois1000"] = rois_leg(1000, a.seed, 20, 5)
+        log("rois1000", out["rois1000"])
+        out["serve_mix"] = serve_leg(a, a.serve_requests, modes=("device",),
+                                     ct0=V0 if (gen == "ct" and shape == (512, 512, 512)) else None)["device"]
+        out["serve_mix"]["requests"] = a.serve_requests
+        log("serve_mix", out["serve_mix"])
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(V0, K)
     print(json.dumps(out), flush=True)

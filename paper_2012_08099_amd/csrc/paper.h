@@ -26,7 +26,7 @@ constexpr int DRT_KMAX = 4;
 constexpr int PP_WAVES = 8;
 constexpr int PP_ZW = 8;
 constexpr int PP_BZ = PP_WAVES * PP_ZW;  // 64
-constexpr int PP_BY = 8;
+constexpr int PP_BY = 16;
 constexpr int PP_XT = 512;
 constexpr int PP_DW = PP_XT + PP_BZ - 1;  // bins of an X+Z / X-Z partial row
 
@@ -35,7 +35,7 @@ constexpr int PP_DW = PP_XT + PP_BZ - 1;  // bins of an X+Z / X-Z partial row
 //   xy  [nzb][M][L]            XY partial over the z-block zb
 //   xpz [nzb][nxt][M][PP_DW]   X+Z partial: bin s of (zb, xt) is column x0 + z0 + s
 //   xmz [nzb][nxt][M][PP_DW]   X-Z partial: bin s is column x0 - z0 + N - PP_BZ + s
-//   zx  [nyb][L][N]            ZX partial over the y-block yb, stored [x][z]
+//   zx  [nyb][N][L]            ZX partial over the y-block yb, stored [z][x]
 //   yz  [nxt][N][M]            YZ partial over the x-tile xt, stored [z][y]
 struct PaperProjArgs {
     const uint8_t *vol;
@@ -81,6 +81,16 @@ struct DrtArgs {
 
 hipError_t launch_drt_tiles(const DrtArgs &a, hipStream_t st);
 
+// m1d[e][g][n] = sum over the tiles of image e of part1d[tile][g][n], in tile order (one
+// wave per (image, g, n)).
+struct DrtSumArgs {
+    const __int128 *part1d;
+    int32_t tile0[DRT_MAXIMG + 1];
+    int32_t nimg;
+    __int128 *m1d;              // [DRT_MAXIMG][DRT_NDIR][DRT_KMAX + 1]
+};
+hipError_t launch_drt_sum(const DrtSumArgs &a, hipStream_t st);
+
 // Exact inverse of the 1D-to-2D system of order n over the directions (a_g, b_g), g <= n:
 //   m_g,n = sum_p C(n, p) a_g^p b_g^(n-p) M_{p, n-p}
 //   M_{p, n-p} = sum_g num[n][p][g] m_g,n / den[n][p],  den = 2^shift * odd,
@@ -91,12 +101,10 @@ struct DrtSolve {
     uint64_t inv_lo[DRT_KMAX + 1][DRT_KMAX + 1], inv_hi[DRT_KMAX + 1][DRT_KMAX + 1];
 };
 
-// Paper finish: per image, the tiles' 1D moments summed in tile order, solved into the
-// 2D moments; X-Z shifted to its origin N - 1 (Section 5); eqs. 10-16 (15/16 with their
+// Paper finish: per image, the summed 1D moments solved into the 2D moments; X-Z shifted to its origin N - 1 (Section 5); eqs. 10-16 (15/16 with their
 // left-hand sides exchanged) give the 3D moments.
 struct PaperFinishArgs {
-    const __int128 *part1d;
-    int32_t tile0[PAPER_NIMG + 1];
+    const __int128 *m1d;        // DrtSumArgs::m1d
     int32_t nimg, ndir, K;
     int64_t xhat;               // N - 1
     DrtSolve solve;
@@ -109,8 +117,7 @@ hipError_t launch_paper_finish(const PaperFinishArgs &a, hipStream_t st);
 // origins, written into the tile partials the recombination kernel reads -- one tile per
 // image, in slot 2d + 1 -- as nlr 32-bit limbs: part[d][k][q][nlr].
 struct DrtToPartArgs {
-    const __int128 *part1d;
-    int32_t tile0[NDIR_MAX + 1];
+    const __int128 *m1d;        // DrtSumArgs::m1d
     int32_t nimg, ndir, K, nlr;
     DrtSolve solve;
     uint32_t *part;

@@ -143,7 +143,7 @@ struct PaperPlan {
     int64_t W[PAPER_NIMG] = {}, H[PAPER_NIMG] = {};
     size_t img_off[PAPER_NIMG] = {};  // int32 offsets in the image block
     size_t img_bytes = 0;
-    size_t o_xy = 0, o_xpz = 0, o_xmz = 0, o_zx = 0, o_yz = 0, o_p1 = 0, ws = 0;  // workspace, after images
+    size_t o_xy = 0, o_xpz = 0, o_xmz = 0, o_zx = 0, o_yz = 0, o_p1 = 0, o_m1 = 0, ws = 0;  // workspace, after images
     int32_t tile0[PAPER_NIMG + 1] = {};
     int32_t tiles_i[PAPER_NIMG] = {};
 };
@@ -202,6 +202,8 @@ int paper_plan(const int64_t dims[3], dpm_dtype dtype, int K, const void *vol, P
     o += al((size_t)p.nxt * p.N * p.M * 4);
     p.o_p1 = o;
     o += al((size_t)t * DRT_NDIR * (DRT_KMAX + 1) * 16);
+    p.o_m1 = o;
+    o += al((size_t)DRT_MAXIMG * DRT_NDIR * (DRT_KMAX + 1) * 16);
     p.ws = o;
     return DPM_OK;
 }
@@ -298,9 +300,14 @@ int dpm_moments_paper(const void *volume, const int64_t dims[3], dpm_dtype dtype
     d.K = p.K;
     d.part1d = reinterpret_cast<__int128 *>(ws + p.o_p1);
     if ((e = launch_drt_tiles(d, st)) != hipSuccess) return hip_fail(e);
+    DrtSumArgs sa{};
+    sa.part1d = d.part1d;
+    for (int i = 0; i <= p.nimg; ++i) sa.tile0[i] = p.tile0[i];
+    sa.nimg = p.nimg;
+    sa.m1d = reinterpret_cast<__int128 *>(ws + p.o_m1);
+    if ((e = launch_drt_sum(sa, st)) != hipSuccess) return hip_fail(e);
     PaperFinishArgs f{};
-    f.part1d = d.part1d;
-    for (int i = 0; i <= p.nimg; ++i) f.tile0[i] = p.tile0[i];
+    f.m1d = sa.m1d;
     f.nimg = p.nimg;
     f.ndir = p.ndir;
     f.K = p.K;
@@ -333,7 +340,7 @@ size_t dpm_drt_workspace_bytes(const int64_t dims[3], dpm_dtype dtype, int max_o
     }
     const int K1 = max_order + 1;
     return al(imgs * 4) + al(fam) + al((size_t)tiles * DRT_NDIR * (DRT_KMAX + 1) * 16) +
-           al((size_t)K1 * K1 * K1 * info.limbs_moment * 4);
+           al((size_t)DRT_MAXIMG * DRT_NDIR * (DRT_KMAX + 1) * 16) + al((size_t)K1 * K1 * K1 * info.limbs_moment * 4);
 }
 
 int dpm_moments_drt(const void *volume, const int64_t dims[3], dpm_dtype dtype, int max_order,
@@ -376,7 +383,9 @@ int dpm_moments_drt(const void *volume, const int64_t dims[3], dpm_dtype dtype, 
     int32_t *images = reinterpret_cast<int32_t *>(base);
     uint8_t *fws = base + al(imgs * 4);
     __int128 *p1 = reinterpret_cast<__int128 *>(fws + al(fam));
-    uint32_t *part = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(p1) + al((size_t)t * DRT_NDIR * (DRT_KMAX + 1) * 16));
+    __int128 *m1 = reinterpret_cast<__int128 *>(reinterpret_cast<uint8_t *>(p1) + al((size_t)t * DRT_NDIR * (DRT_KMAX + 1) * 16));
+    uint32_t *part = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(m1) +
+                                                  al((size_t)DRT_MAXIMG * DRT_NDIR * (DRT_KMAX + 1) * 16));
     // step 1: the family projection images (Section 3.1)
     if ((rc = dpm::family_images(volume, dims, dtype, K, images, fws, fam, st, nullptr))) return rc;
     // step 2 by the 1D integrals of Section 5
@@ -388,9 +397,14 @@ int dpm_moments_drt(const void *volume, const int64_t dims[3], dpm_dtype dtype, 
     d.part1d = p1;
     hipError_t e = launch_drt_tiles(d, st);
     if (e != hipSuccess) return hip_fail(e);
+    DrtSumArgs sa{};
+    sa.part1d = p1;
+    for (int i = 0; i <= nd; ++i) sa.tile0[i] = i < nd ? d.im[i].tile0 : t;
+    sa.nimg = nd;
+    sa.m1d = m1;
+    if ((e = launch_drt_sum(sa, st)) != hipSuccess) return hip_fail(e);
     DrtToPartArgs tp{};
-    tp.part1d = p1;
-    for (int i = 0; i <= NDIR_MAX; ++i) tp.tile0[i] = i <= nd ? (i < nd ? d.im[i].tile0 : t) : t;
+    tp.m1d = m1;
     tp.nimg = nd;
     tp.ndir = nd;
     tp.K = K;

@@ -27,12 +27,6 @@ namespace dpm {
 
 namespace {
 
-__device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
-#pragma unroll
-    for (int s = 1; s < 64; s <<= 1) v += __shfl_xor(v, s, 64);
-    return v;
-}
-
 __device__ __forceinline__ long long wave_sum_i64(long long v) {
 #pragma unroll
     for (int s = 1; s < 64; s <<= 1) v += __shfl_xor(v, s, 64);
@@ -49,12 +43,13 @@ __device__ __forceinline__ __int128 wave_sum_i128(__int128 v) {
     return v;
 }
 
-// 8 voxels of row (y, z) from x = xl on (or zeros where outside the volume).  FAST: L is
-// a multiple of 8 and rows are aligned to one lane's load (16 bytes u16, 8 bytes u8).
+// 8 voxels of row (y, z) from x = xl on, packed as they are in memory (4 dwords for
+// uint16, 2 for uint8), zeros where outside the volume.  FAST: L is a multiple of 8 and
+// rows are aligned to one lane's load (16 bytes uint16, 8 bytes uint8).
 template <typename T, bool FAST>
-__device__ __forceinline__ void load8(const PaperProjArgs &a, int64_t y, int64_t z, int64_t xl, int32_t (&v)[8]) {
+__device__ __forceinline__ void load8(const PaperProjArgs &a, int64_t y, int64_t z, int64_t xl, uint32_t (&w)[4]) {
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = 0;
+    for (int k = 0; k < 4; ++k) w[k] = 0u;
     if (z >= a.N || xl >= a.L) return;
     const T *row = reinterpret_cast<const T *>(a.vol) + (z * a.M + y) * a.L;
     if (FAST) {
@@ -62,23 +57,53 @@ __device__ __forceinline__ void load8(const PaperProjArgs &a, int64_t y, int64_t
         typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
         if (sizeof(T) == 2) {
             const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(row + xl));
-            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                v[2 * k] = (int32_t)(w[k] & 0xffffu);
-                v[2 * k + 1] = (int32_t)(w[k] >> 16);
-            }
+            w[0] = q.x;
+            w[1] = q.y;
+            w[2] = q.z;
+            w[3] = q.w;
         } else {
             const u32x2 q = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(row + xl));
-            const uint32_t w[2] = {q.x, q.y};
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = (int32_t)((w[k / 4] >> (8 * (k % 4))) & 0xffu);
+            w[0] = q.x;
+            w[1] = q.y;
         }
     } else {
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            if (xl + k < a.L) v[k] = (int32_t)row[xl + k];
+            if (xl + k < a.L) {
+                const uint32_t e = row[xl + k];
+                if (sizeof(T) == 2) w[k / 2] |= e << (16 * (k % 2));
+                else w[k / 4] |= e << (8 * (k % 4));
+            }
     }
+}
+
+template <typename T>
+__device__ __forceinline__ int32_t voxel_of(const uint32_t (&w)[4], int k) {
+    if (sizeof(T) == 2) return (int32_t)((w[k / 2] >> (16 * (k % 2))) & 0xffffu);
+    return (int32_t)((w[k / 4] >> (8 * (k % 4))) & 0xffu);
+}
+
+// The 8 values r[0..7] of every lane summed over the wave: lane 8 z (z < 8) ends up
+// holding the sum for z.  Halving exchanges: 4 + 2 + 1 shuffles pair up the values, 3
+// more finish the sums (10 shuffles instead of 8 full reductions).
+__device__ __forceinline__ int32_t wave_sum8(const int32_t (&r)[8], int lane) {
+    int32_t a4[4], a2[2];
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int32_t keep = b5 ? r[q + 4] : r[q], send = b5 ? r[q] : r[q + 4];
+        a4[q] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int32_t keep = b4 ? a4[q + 2] : a4[q], send = b4 ? a4[q] : a4[q + 2];
+        a2[q] = keep + __shfl_xor(send, 16, 64);
+    }
+    int32_t a1 = (b3 ? a2[1] : a2[0]) + __shfl_xor(b3 ? a2[0] : a2[1], 8, 64);
+    a1 += __shfl_xor(a1, 4, 64);
+    a1 += __shfl_xor(a1, 2, 64);
+    a1 += __shfl_xor(a1, 1, 64);
+    return a1;  // lane l: value index (l >> 3) & 7, when l % 8 == 0
 }
 
 template <typename T, bool FAST>
@@ -109,7 +134,7 @@ __global__ void __launch_bounds__(PP_WAVES * 64) paper_project_kernel(PaperProjA
     for (int yy = 0; yy < PP_BY; ++yy) {
         const int64_t y = y0 + yy;
         if (y >= a.M) break;  // the same for the whole workgroup
-        int32_t v[PP_ZW][8];
+        uint32_t v[PP_ZW][4];
 #pragma unroll
         for (int zz = 0; zz < PP_ZW; ++zz) load8<T, FAST>(a, y, zw0 + zz, xl, v[zz]);
         int32_t xy[8], wp[8 + PP_ZW - 1], wm[8 + PP_ZW - 1], rs[PP_ZW];
@@ -122,7 +147,7 @@ __global__ void __launch_bounds__(PP_WAVES * 64) paper_project_kernel(PaperProjA
             int32_t s = 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const int32_t e = v[zz][k];
+                const int32_t e = voxel_of<T>(v[zz], k);
                 xy[k] += e;                  // I(x, y), eq. 5: summed over z
                 zx[zz][k] += e;              // I(z, x), eq. 7: summed over y
                 s += e;                      // I(y, z), eq. 6: summed over x
@@ -146,11 +171,11 @@ __global__ void __launch_bounds__(PP_WAVES * 64) paper_project_kernel(PaperProjA
             for (int s = 0; s < 8 + PP_ZW - 1; ++s)
                 if (wm[s]) atomicAdd(&s_xmz[yy][bm + s], wm[s]);
         }
-#pragma unroll
-        for (int zz = 0; zz < PP_ZW; ++zz) {
-            const int32_t t = wave_sum_i32(rs[zz]);
-            const int64_t z = zw0 + zz;
-            if (lane == 0 && z < a.N) a.yz[((int64_t)xt * a.N + z) * a.M + y] = t;
+        {
+            static_assert(PP_ZW == 8, "wave_sum8 reduces 8 planes");
+            const int32_t t = wave_sum8(rs, lane);
+            const int64_t z = zw0 + (lane >> 3);
+            if ((lane & 7) == 0 && z < a.N) a.yz[((int64_t)xt * a.N + z) * a.M + y] = t;
         }
     }
     // ZX partial of this y-block: [yb][z][x], 8 consecutive x per lane
@@ -178,29 +203,20 @@ __global__ void __launch_bounds__(PP_WAVES * 64) paper_project_kernel(PaperProjA
     }
 }
 
-// One thread per image pixel (images XY, YZ, X+Z, X-Z) or per 64 x 64 block of ZX
-// (transposed through LDS); partials summed in ascending block order.
+// One thread per image pixel; partials summed in ascending block order.
 __global__ void __launch_bounds__(256) paper_reduce_kernel(PaperReduceArgs a) {
     const int e = blockIdx.y, tid = threadIdx.x;
     if (e >= a.nimg) return;
     const int64_t L = a.L, M = a.M, N = a.N, DW = PP_DW;
     if (e == 2) {
-        __shared__ int32_t tile[64][65];
-        const int64_t tz = (N + 63) / 64, tx = (L + 63) / 64;
-        if ((int64_t)blockIdx.x >= tz * tx) return;
-        const int64_t bz = blockIdx.x / tx * 64, bx = blockIdx.x % tx * 64;
-        for (int i = tid; i < 64 * 64; i += 256) {
-            const int zz = i / 64, xx = i % 64;
-            int32_t s = 0;
-            if (bz + zz < N && bx + xx < L)
-                for (int yb = 0; yb < a.nyb; ++yb) s += a.zx[((int64_t)yb * N + bz + zz) * L + bx + xx];
-            tile[zz][xx] = s;
-        }
-        __syncthreads();
-        for (int i = tid; i < 64 * 64; i += 256) {
-            const int xx = i / 64, zz = i % 64;
-            if (bz + zz < N && bx + xx < L) a.img[2][(bx + xx) * N + bz + zz] = tile[zz][xx];  // [j = x][i = z]
-        }
+        // ZX[x][z] = sum over y-blocks of the [z][x] partials: reads along x, one
+        // transposed store per element
+        const int64_t el = (int64_t)blockIdx.x * 256 + tid;
+        if (el >= N * L) return;
+        const int64_t z = el / L, x = el % L;
+        int32_t s = 0;
+        for (int yb = 0; yb < a.nyb; ++yb) s += a.zx[((int64_t)yb * N + z) * L + x];
+        a.img[2][x * N + z] = s;  // [j = x][i = z]
         return;
     }
     const int64_t W = e == 0 ? L : e == 1 ? M : L + N - 1;
@@ -251,11 +267,18 @@ __global__ void __launch_bounds__(256) drt_tile_kernel(DrtArgs a) {
     }
     __syncthreads();
     const int64_t i = i0 + tid;
-    long long vert = 0;
+    // all rows of the tile in flight at once
+    int32_t col[DRT_RB];
+#pragma unroll
     for (int jj = 0; jj < DRT_RB; ++jj) {
         const int64_t j = j0 + jj;
-        if (j >= im.H) break;  // the same for the whole workgroup
-        const long long v = i < im.W ? (long long)im.img[j * im.W + i] : 0;
+        col[jj] = (i < im.W && j < im.H) ? im.img[j * im.W + i] : 0;
+    }
+    long long vert = 0;
+#pragma unroll
+    for (int jj = 0; jj < DRT_RB; ++jj) {
+        if (j0 + jj >= im.H) break;  // the same for the whole workgroup
+        const long long v = col[jj];
         vert += v;                                       // Vert[i]
         const long long hs = wave_sum_i64(v);
         if (lane == 0 && hs) atomicAdd((unsigned long long *)&s_hor[jj], (unsigned long long)hs);  // Horiz[j]
@@ -306,16 +329,19 @@ __global__ void __launch_bounds__(256) drt_tile_kernel(DrtArgs a) {
     }
 }
 
-// m[e][g][n]: the tiles' 1D moments of image e summed in tile order (LDS of the caller).
-__device__ void sum_tiles(const __int128 *part1d, const int32_t *tile0, int nimg, __int128 (*m)[DRT_NDIR][DRT_KMAX + 1]) {
-    const int tid = threadIdx.x;
+__global__ void __launch_bounds__(64) drt_sum_kernel(DrtSumArgs a) {
+    const int e = blockIdx.x, gn = blockIdx.y, lane = threadIdx.x;
     constexpr int NV = DRT_NDIR * (DRT_KMAX + 1);
-    for (int v = tid; v < nimg * NV; v += blockDim.x) {
-        const int e = v / NV, gn = v % NV;
-        __int128 s = 0;
-        for (int t = tile0[e]; t < tile0[e + 1]; ++t) s += part1d[(int64_t)t * NV + gn];
-        m[e][gn / (DRT_KMAX + 1)][gn % (DRT_KMAX + 1)] = s;
-    }
+    __int128 s = 0;
+    for (int t = a.tile0[e] + lane; t < a.tile0[e + 1]; t += 64) s += a.part1d[(int64_t)t * NV + gn];
+    s = wave_sum_i128(s);
+    if (lane == 0) a.m1d[(int64_t)e * NV + gn] = s;
+}
+
+__device__ void load_m1d(const __int128 *m1d, int nimg, __int128 (*m)[DRT_NDIR][DRT_KMAX + 1]) {
+    constexpr int NV = DRT_NDIR * (DRT_KMAX + 1);
+    for (int v = threadIdx.x; v < nimg * NV; v += blockDim.x)
+        m[v / NV][(v % NV) / (DRT_KMAX + 1)][v % (DRT_KMAX + 1)] = m1d[v];
 }
 
 // 2D moment M_{p,q} of an image from its 1D moments (exact).
@@ -345,7 +371,7 @@ __device__ __forceinline__ void put_i128(void *exact, double *fp64, int idx, __i
 
 __global__ void __launch_bounds__(256) paper_finish_kernel(PaperFinishArgs a) {
     __shared__ __int128 m[PAPER_NIMG][DRT_NDIR][DRT_KMAX + 1];
-    sum_tiles(a.part1d, a.tile0, a.nimg, m);
+    load_m1d(a.m1d, a.nimg, m);
     __syncthreads();
     const int idx = threadIdx.x;
     if (idx >= n_moments(a.K)) return;
@@ -391,7 +417,7 @@ __global__ void __launch_bounds__(256) paper_finish_kernel(PaperFinishArgs a) {
 
 __global__ void __launch_bounds__(256) drt_to_part_kernel(DrtToPartArgs a) {
     __shared__ __int128 m[NDIR_MAX][DRT_NDIR][DRT_KMAX + 1];
-    sum_tiles(a.part1d, a.tile0, a.nimg, m);
+    load_m1d(a.m1d, a.nimg, m);
     __syncthreads();
     const int K = a.K, K1 = K + 1;
     for (int v = threadIdx.x; v < a.nimg * K1 * K1; v += blockDim.x) {
@@ -420,7 +446,7 @@ hipError_t launch_paper_reduce(const PaperReduceArgs &a, hipStream_t st) {
     const int64_t W34 = a.L + a.N - 1;
     int64_t blocks = std::max<int64_t>(std::max<int64_t>(a.L * a.M, a.M * a.N), W34 * a.M);
     blocks = (blocks + 255) / 256;
-    blocks = std::max<int64_t>(blocks, ((a.N + 63) / 64) * ((a.L + 63) / 64));
+    blocks = std::max<int64_t>(blocks, (a.N * a.L + 255) / 256);
     if (blocks > INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(paper_reduce_kernel, dim3((unsigned)blocks, a.nimg), dim3(256), 0, st, a);
     return hipGetLastError();
@@ -429,6 +455,11 @@ hipError_t launch_paper_reduce(const PaperReduceArgs &a, hipStream_t st) {
 hipError_t launch_drt_tiles(const DrtArgs &a, hipStream_t st) {
     if (a.ntiles <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(drt_tile_kernel, dim3(a.ntiles), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_drt_sum(const DrtSumArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(drt_sum_kernel, dim3(a.nimg, DRT_NDIR * (DRT_KMAX + 1)), dim3(64), 0, st, a);
     return hipGetLastError();
 }
 
