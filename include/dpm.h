@@ -307,10 +307,20 @@ int dpm_profile_collect(dpm_profile *out);
  * flight.  Results are copied to the caller's host buffers before the completion is
  * reported.
  *
+ * Requests of one batched launch have the same order (a batch takes waiting small
+ * requests of the first one's order, in arrival order).
  * Ownership: the caller keeps `data` and the output buffers of a request valid until
  * its completion has been returned by dpm_server_poll.  A request's `data` may be host
  * memory (copied to the arena) or device memory on the server's device (read in place;
- * batched requests are copied into a packed arena block first).
+ * batched requests are copied into a packed arena block first).  Device data must be
+ * complete when the server reads it: pass `ready_event` (recorded on the stream that
+ * writes it), or finish writing before submitting.
+ * Residency: with keep_resident = 1 the request's 2D moments of every side of every
+ * projection image (eq. 1 of the images of Section 3.1; 2 (K+1)^3 exact integers) stay in
+ * the arena after completion, under the request's tag.  dpm_server_requery recombines
+ * them (Section 3.2) for any order <= K without reading the volume again.  Entries are
+ * evicted least recently used (a query counts as a use) whenever a request cannot be
+ * admitted otherwise, or dropped by dpm_server_release.
  * Thread safety: submit and poll may be called from any threads.
  * Errors: submit returns DPM_EINVAL for a malformed request and DPM_ERANGE if it cannot
  * fit the budget; a request that fails on the device completes with its status. */
@@ -331,12 +341,16 @@ typedef struct {
     int32_t dtype;           /* dpm_dtype                                               */
     int64_t dims[3];         /* L, M, N                                                 */
     int32_t max_order;       /* 0..16 (batched only when <= 6)                          */
-    int32_t reserved;
-    uint64_t tag;            /* returned with the completion                            */
+    int32_t keep_resident;   /* 1: keep the request's image moments on the device after
+                                completion, for dpm_server_requery (see below)          */
+    uint64_t tag;            /* returned with the completion; names a resident entry    */
     double t_arrival_ms;     /* arrival time on the server clock (dpm_server_now_ms);
                                 <= 0: the submit time                                  */
     dpm_i128 *exact;         /* host, n_moments(min(K,4)) entries, or NULL              */
     double *fp64;            /* host, n_moments(K) entries, or NULL                     */
+    void *ready_event;       /* device data only: a hipEvent_t recorded after the work
+                                that writes `data`; the server's stream waits for it
+                                before reading.  NULL: `data` is complete at submit.   */
 } dpm_request;
 
 typedef struct {
@@ -352,6 +366,7 @@ typedef struct {
     int64_t submitted, completed, batched_jobs, single_jobs;
     int64_t arena_bytes, arena_peak_used;
     int32_t pending, inflight;
+    int64_t resident, resident_bytes, evictions;  /* resident entries (see requery) */
 } dpm_server_stats;
 
 /* Milliseconds on the server clock (monotonic). */
@@ -366,6 +381,13 @@ int dpm_server_stats_get(dpm_server *s, dpm_server_stats *out);
  * clock (sleeping, then spinning for the last 0.2 ms), and returns once all are
  * submitted (or the first failing submit's status).  Arrival times must not decrease. */
 int dpm_server_replay(dpm_server *s, const dpm_request *reqs, int n);
+/* Moments of order <= max_order (<= the request's order) of a resident request, from its
+ * resident image moments: exact / fp64 are HOST buffers as in dpm_request (either may be
+ * NULL).  Blocking (runs on a stream of the server).  DPM_EINVAL if `tag` is not resident
+ * (never kept, evicted or released) or max_order exceeds its order. */
+int dpm_server_requery(dpm_server *s, uint64_t tag, int max_order, dpm_i128 *exact, double *fp64);
+/* Drop a resident entry (DPM_EINVAL if `tag` is not resident). */
+int dpm_server_release(dpm_server *s, uint64_t tag);
 /* Waits for every submitted request, then frees the server (completions not yet
  * polled are dropped). */
 int dpm_server_destroy(dpm_server *s);

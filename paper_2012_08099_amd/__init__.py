@@ -385,10 +385,13 @@ def release():
 class Server:
     """The served loop of ``dpm_server_*`` (argument marshalling only).
 
-    ``submit`` takes a contiguous uint8/uint16 array -- a device tensor (read in place)
-    or a host tensor / numpy array (copied into the server's arena; pinned memory keeps
-    that copy asynchronous) -- and returns a tag.  The input and the result arrays are
-    kept alive here until ``poll`` has returned the request's completion.
+    ``submit`` takes a contiguous uint8/uint16 array -- a device tensor (read in place,
+    after the work queued so far on torch's current stream: an event recorded there is
+    passed with the request) or a host tensor / numpy array (copied into the server's
+    arena; pinned memory keeps that copy asynchronous) -- and returns a tag.  The input
+    and the result arrays are kept alive here until ``poll`` has returned the request's
+    completion.  ``keep=True`` keeps the request's image moments resident for
+    ``requery``.
     """
 
     def __init__(self, hbm_budget=8 << 30, n_streams=4, batch_voxels=128 ** 3, batch_max=256,
@@ -405,15 +408,15 @@ class Server:
     def now_ms():
         return lib().dpm_server_now_ms()
 
-    def submit(self, vol, K, t_arrival_ms=0.0):
-        req = self._request(vol, K, t_arrival_ms)
+    def submit(self, vol, K, t_arrival_ms=0.0, keep=False):
+        req = self._request(vol, K, t_arrival_ms, keep)
         rc = lib().dpm_server_submit(self._h, ctypes.byref(req))
         if rc:
             self._live.pop(req.tag, None)
             raise DpmError(rc, "dpm_server_submit")
         return req.tag
 
-    def _request(self, vol, K, t_arrival_ms):
+    def _request(self, vol, K, t_arrival_ms, keep=False):
         import numpy as np
         import torch
         if isinstance(vol, np.ndarray):
@@ -434,7 +437,15 @@ class Server:
         req.t_arrival_ms = float(t_arrival_ms)
         req.exact = exact.ctypes.data
         req.fp64 = fp.ctypes.data
-        self._live[tag] = (vol, exact, fp, K)
+        req.keep_resident = 1 if keep else 0
+        ev = None
+        if vol.is_cuda:
+            # the server's stream waits for what torch has queued so far (e.g. the
+            # kernel that wrote the volume)
+            ev = torch.cuda.Event()
+            ev.record(torch.cuda.current_stream(vol.device))
+            req.ready_event = ev.cuda_event
+        self._live[tag] = (vol, exact, fp, K, ev)
         return req
 
     def replay(self, items):
@@ -456,12 +467,25 @@ class Server:
             raise DpmError(n, "dpm_server_poll")
         out = []
         for c in buf[:n]:
-            vol, exact, fp, K = self._live.pop(c.tag)
+            vol, exact, fp, K, _ = self._live.pop(c.tag)
             ex = [i128_to_int(int(lo) & (2 ** 64 - 1), int(hi)) for lo, hi in exact.tolist()]
             out.append({"tag": c.tag, "status": c.status, "batched": bool(c.batched),
                         "t_arrival_ms": c.t_arrival_ms, "t_start_ms": c.t_start_ms, "t_done_ms": c.t_done_ms,
                         "moments": Moments(K, ex, fp)})
         return out
+
+    def requery(self, tag, K):
+        """Moments of order <= K of a completed request submitted with keep=True, from its
+        resident image moments (no volume read).  Returns ``Moments``."""
+        exact = np.zeros((num_moments(min(K, 4)), 2), dtype=np.int64)
+        fp = np.zeros(num_moments(K), dtype=np.float64)
+        check(lib().dpm_server_requery(self._h, int(tag), int(K), exact.ctypes.data, fp.ctypes.data),
+              "dpm_server_requery")
+        ex = [i128_to_int(int(lo) & (2 ** 64 - 1), int(hi)) for lo, hi in exact.tolist()]
+        return Moments(K, ex, fp)
+
+    def release_resident(self, tag):
+        check(lib().dpm_server_release(self._h, int(tag)), "dpm_server_release")
 
     def stats(self):
         s = _lib.ServerStats()

@@ -76,9 +76,9 @@ class ServerConfig(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("data_on_device", ctypes.c_int32), ("dtype", ctypes.c_int32),
-                ("dims", ctypes.c_int64 * 3), ("max_order", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dims", ctypes.c_int64 * 3), ("max_order", ctypes.c_int32), ("keep_resident", ctypes.c_int32),
                 ("tag", ctypes.c_uint64), ("t_arrival_ms", ctypes.c_double), ("exact", ctypes.c_void_p),
-                ("fp64", ctypes.c_void_p)]
+                ("fp64", ctypes.c_void_p), ("ready_event", ctypes.c_void_p)]
 
 
 class Completion(ctypes.Structure):
@@ -89,7 +89,8 @@ class Completion(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("batched_jobs", ctypes.c_int64),
                 ("single_jobs", ctypes.c_int64), ("arena_bytes", ctypes.c_int64), ("arena_peak_used", ctypes.c_int64),
-                ("pending", ctypes.c_int32), ("inflight", ctypes.c_int32)]
+                ("pending", ctypes.c_int32), ("inflight", ctypes.c_int32), ("resident", ctypes.c_int64),
+                ("resident_bytes", ctypes.c_int64), ("evictions", ctypes.c_int64)]
 
 
 Dims = ctypes.c_int64 * 3
@@ -148,6 +149,9 @@ SIGNATURES = {
     "dpm_server_stats_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
     "dpm_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "dpm_server_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.c_int]),
+    "dpm_server_requery": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
+    "dpm_server_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
 }
 
 _lib = None

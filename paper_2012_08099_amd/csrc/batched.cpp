@@ -357,6 +357,20 @@ bool build_and_launch_graph(const GraphKey &key, const BPlan &p, const PowTab &p
 }  // namespace
 
 namespace dpm {
+// Where a batched call leaves ROI i's power-sum tiles: byte offsets (in the workspace) of
+// the tile partials and of the ROI's device descriptor, and the limbs.
+int batched_partials(const dpm_roi *rois, int n_rois, int max_order, int i, size_t *part_off, size_t *rd_off,
+                     int *nlr) {
+    BPlan p;
+    int rc = bplan(rois, n_rois, max_order, p);
+    if (rc) return rc;
+    if (i < 0 || i >= n_rois) return DPM_EINVAL;
+    *part_off = p.off_part;
+    *rd_off = p.off_rd + sizeof(RoiDesc) * (size_t)i;
+    *nlr = p.nlr;
+    return DPM_OK;
+}
+
 // Frees the pinned staging buffers (called by dpm_release).
 int batched_release() {
     {

@@ -655,6 +655,19 @@ int family_images(const void *volume, const int64_t dims[3], dpm_dtype dtype, in
     return run_plan(p, volume, images, off, w, nullptr, nullptr, ws, st);
 }
 
+// Where a dpm_moments_async call of this request leaves its power-sum tiles in the
+// workspace: byte offset of the tile partials, the tile range of every slot and the limbs.
+int single_partials(const int64_t dims[3], dpm_dtype dtype, int max_order, size_t *part_off,
+                    int32_t tile0[NSLOT + 1], int *nlr) {
+    Plan p;
+    int rc = make_plan(dims, dtype, max_order, false, p, nullptr);
+    if (rc) return rc;
+    *part_off = p.rows_bytes;
+    for (int s = 0; s <= NSLOT; ++s) tile0[s] = p.rl.tile0[s];
+    *nlr = p.nlr;
+    return DPM_OK;
+}
+
 int batched_release();  // batched.cpp
 int batched_powtab(int amax, int K, PowTab &out) { return get_powtab(amax, K, out); }
 bool batched_pow_columns(int amax, int K, int32_t colstart[KMAX + 2]) { return pow_columns(amax, K, colstart); }

@@ -9,6 +9,13 @@
 // flight, and retires jobs whose completion event has fired: results are copied from
 // pinned staging into the caller's buffers, arena blocks are released, and a
 // completion is queued for poll().
+//
+// Residency: a request submitted with keep_resident keeps, after completion, the 2D
+// moments of each side of each of its projection images (collapsed from the power-sum
+// tiles by a small kernel on the job's stream) in an arena block.  Such entries are
+// evicted least recently used first when a job cannot be admitted otherwise; a query
+// recombines an entry (Section 3.2) for any order up to the request's without reading
+// the volume again.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,10 +30,17 @@
 
 #include "../../include/dpm.h"
 #include "dpm_common.h"
+#include "kernels.h"
+#include "resident.h"
 
 namespace dpm {
 int batched_run(const void *packed, const dpm_roi *rois, int n_rois, int max_order, const dpm_out *out_device,
                 void *workspace, size_t ws_bytes, void *stream, bool allow_graphs);  // batched.cpp
+int batched_partials(const dpm_roi *rois, int n_rois, int max_order, int i, size_t *part_off, size_t *rd_off,
+                     int *nlr);  // batched.cpp
+int single_partials(const int64_t dims[3], dpm_dtype dtype, int max_order, size_t *part_off,
+                    int32_t tile0[NSLOT + 1], int *nlr);  // dpm_api.cpp
+int batched_ensure_tables();  // dpm_api.cpp
 }  // namespace dpm
 
 namespace {
@@ -108,7 +122,22 @@ struct Job {
     size_t res_off = 0;  // pinned results: exact [n][nm4] then fp64 [n][nm]
     double t_start = 0;
     int status = DPM_OK;
+    int nlr = 4;                 // limbs of the 2D moments (resident blocks)
+    std::vector<int> keep_bi;    // per request: index in blocks of its resident block, or -1
 };
+
+// 2D moments kept on the device after completion: slot-collapsed tiles, order K.
+struct Resident {
+    size_t off = 0, n = 0;
+    int K = 0, nlr = 4;
+    uint64_t tick = 0;
+};
+
+size_t resident_bytes(int K, int nlr) { return (size_t)2 * (K + 1) * (K + 1) * (K + 1) * nlr * 4; }
+
+// Query scratch allocated at creation: re-strided 2D moments and the outputs.
+constexpr size_t kQueryPart = 2 * 17 * 17 * 17 * 12 * 4;
+constexpr size_t kQueryOut = 35 * 16 + 969 * 8;
 
 }  // namespace
 
@@ -134,6 +163,17 @@ struct dpm_server {
     // statistics (under mu)
     dpm_server_stats st{};
 
+    // resident 2D moments; the map and the device arena are guarded by res_mu (the worker
+    // and the query / release calls of other threads touch them)
+    std::mutex res_mu;
+    std::map<uint64_t, Resident> resident;
+    uint64_t res_tick = 0;
+    hipStream_t qstream = nullptr;   // queries
+    uint8_t *qdev = nullptr;         // query scratch (device, outside the arena)
+    uint8_t *qhost = nullptr;        // pinned query results
+
+    bool evict_one();
+
     size_t pin_bytes_per_job() const {
         const size_t b = (size_t)cfg.batch_max * (size_t)(dpm::n_moments(4) * 16 + dpm::n_moments(6) * 8);
         const size_t s = (size_t)dpm::n_moments(4) * 16 + (size_t)dpm::n_moments(dpm::KMAX) * 8;
@@ -142,10 +182,12 @@ struct dpm_server {
     bool small(const Req &q) const { return q.batchable && q.voxels() <= cfg.batch_voxels; }
 
     void release_blocks(Job &j) {
+        std::lock_guard<std::mutex> lk(res_mu);
         for (auto &b : j.blocks) (b.host ? parena : darena)->release(b.off, b.n);
         j.blocks.clear();
     }
     bool take(Job &j, bool host, size_t n, size_t &off) {
+        std::lock_guard<std::mutex> lk(res_mu);
         if (!(host ? parena : darena)->alloc(n, off)) return false;
         j.blocks.push_back({host, off, n});
         return true;
@@ -161,6 +203,7 @@ bool dpm_server::reserve(Job &j) {
     const int n = (int)j.reqs.size();
     const int nm = dpm::n_moments(j.K), nm4 = dpm::n_moments(std::min(j.K, 4));
     size_t off;
+    j.keep_bi.assign(n, -1);
     if (!take(j, true, pin_bytes_per_job(), j.res_off)) return false;
     if (j.batched) {
         size_t packed = 0;
@@ -175,13 +218,41 @@ bool dpm_server::reserve(Job &j) {
         const size_t ws = dpm_batched_workspace_bytes(rois.data(), n, j.K);
         if (!ws || !take(j, false, ws, off)) return false;
         if (!take(j, false, (size_t)n * (nm4 * 16 + nm * 8), off)) return false;
+        size_t po, ro;
+        if (dpm::batched_partials(rois.data(), n, j.K, 0, &po, &ro, &j.nlr)) return false;
     } else {
         const Req &q = j.reqs[0];
         if (!q.r.data_on_device && !take(j, false, q.bytes(), off)) return false;
         const size_t ws = dpm_workspace_bytes(q.r.dims, (dpm_dtype)q.r.dtype, j.K);
         if (!ws || !take(j, false, ws, off)) return false;
         if (!take(j, false, (size_t)(nm4 * 16 + nm * 8), off)) return false;
+        size_t po;
+        int32_t t0[dpm::NSLOT + 1];
+        if (dpm::single_partials(q.r.dims, (dpm_dtype)q.r.dtype, j.K, &po, t0, &j.nlr)) return false;
     }
+    // blocks that stay after completion: the resident 2D moments of kept requests
+    for (int i = 0; i < n; ++i)
+        if (j.reqs[i].r.keep_resident) {
+            if (!take(j, false, resident_bytes(j.K, j.nlr), off)) return false;
+            j.keep_bi[i] = (int)j.blocks.size() - 1;
+        }
+    return true;
+}
+
+bool dpm_server::evict_one() {
+    std::lock_guard<std::mutex> lk(res_mu);
+    if (resident.empty()) return false;
+    auto victim = resident.begin();
+    for (auto it = resident.begin(); it != resident.end(); ++it)
+        if (it->second.tick < victim->second.tick) victim = it;
+    darena->release(victim->second.off, victim->second.n);
+    resident.erase(victim);
+    std::lock_guard<std::mutex> lk2(mu);
+    st.evictions += 1;
+    st.resident = (int64_t)resident.size();
+    int64_t b = 0;
+    for (auto &kv : resident) b += (int64_t)kv.second.n;
+    st.resident_bytes = b;
     return true;
 }
 
@@ -192,6 +263,12 @@ int dpm_server::launch(Job &j) {
     j.t_start = now_ms_impl();
     size_t bi = 1;  // blocks[0] is the pinned result staging
     hipError_t e = hipSuccess;
+    // device inputs: wait for the work that produces them
+    for (auto &q : j.reqs)
+        if (q.r.data_on_device && q.r.ready_event) {
+            e = hipStreamWaitEvent(s, static_cast<hipEvent_t>(q.r.ready_event), 0);
+            if (e != hipSuccess) return DPM_EDEVICE;
+        }
     if (j.batched) {
         uint8_t *packed = dev + j.blocks[bi++].off;
         std::vector<dpm_roi> rois(n);
@@ -210,6 +287,20 @@ int dpm_server::launch(Job &j) {
                     reinterpret_cast<double *>(dev + ob.off + (size_t)n * nm4 * 16)};
         int rc = dpm::batched_run(packed, rois.data(), n, j.K, &out, dev + wb.off, wb.n, s, false);
         if (rc) return rc;
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+            if (j.keep_bi[i] < 0) continue;
+            size_t po, ro;
+            int nlr;
+            if ((rc = dpm::batched_partials(rois.data(), n, j.K, i, &po, &ro, &nlr))) return rc;
+            dpm::CollapseArgs c{};
+            c.part = reinterpret_cast<const uint32_t *>(dev + wb.off + po);
+            c.roi = reinterpret_cast<const dpm::RoiDesc *>(dev + wb.off + ro);
+            c.K = j.K;
+            c.nlr = nlr;
+            c.out = reinterpret_cast<uint32_t *>(dev + j.blocks[j.keep_bi[i]].off);
+            e = dpm::launch_collapse(c, s);
+        }
+        if (e != hipSuccess) return DPM_EDEVICE;
         e = hipMemcpyAsync(pin + j.res_off, dev + ob.off, (size_t)n * (nm4 * 16 + nm * 8), hipMemcpyDeviceToHost, s);
     } else {
         const Req &q = j.reqs[0];
@@ -225,6 +316,16 @@ int dpm_server::launch(Job &j) {
         dpm_out out{reinterpret_cast<dpm_i128 *>(dev + ob.off), reinterpret_cast<double *>(dev + ob.off + nm4 * 16)};
         int rc = dpm_moments_async(vol, q.r.dims, (dpm_dtype)q.r.dtype, j.K, &out, dev + wb.off, wb.n, s);
         if (rc) return rc;
+        if (j.keep_bi[0] >= 0) {
+            dpm::CollapseArgs c{};
+            size_t po;
+            if ((rc = dpm::single_partials(q.r.dims, (dpm_dtype)q.r.dtype, j.K, &po, c.tile0, &c.nlr))) return rc;
+            c.part = reinterpret_cast<const uint32_t *>(dev + wb.off + po);
+            c.roi = nullptr;
+            c.K = j.K;
+            c.out = reinterpret_cast<uint32_t *>(dev + j.blocks[j.keep_bi[0]].off);
+            if (dpm::launch_collapse(c, s) != hipSuccess) return DPM_EDEVICE;
+        }
         e = hipMemcpyAsync(pin + j.res_off, dev + ob.off, (size_t)(nm4 * 16 + nm * 8), hipMemcpyDeviceToHost, s);
     }
     if (e == hipSuccess) e = hipEventRecord(j.ev, s);
@@ -247,6 +348,33 @@ void dpm_server::finish(Job &j, int status) {
                 std::memcpy(q.r.fp64, res + (size_t)n * nm4 * 16 + (size_t)i * nm * 8, (size_t)dpm::n_moments(k) * 8);
         }
         out.push_back(dpm_completion{q.r.tag, status, j.batched ? 1 : 0, q.t_arr, j.t_start, now_ms_impl()});
+    }
+    if (status == DPM_OK) {
+        // kept requests: their resident blocks leave the job (released on eviction)
+        std::vector<bool> kept(j.blocks.size(), false);
+        {
+            std::lock_guard<std::mutex> lk(res_mu);
+            for (int i = 0; i < n; ++i) {
+                if (j.keep_bi.size() != (size_t)n || j.keep_bi[i] < 0) continue;
+                const Block &b = j.blocks[j.keep_bi[i]];
+                auto old = resident.find(j.reqs[i].r.tag);
+                if (old != resident.end()) {
+                    darena->release(old->second.off, old->second.n);
+                    resident.erase(old);
+                }
+                resident[j.reqs[i].r.tag] = Resident{b.off, b.n, j.K, j.nlr, ++res_tick};
+                kept[j.keep_bi[i]] = true;
+            }
+            int64_t bytes = 0;
+            for (auto &kv : resident) bytes += (int64_t)kv.second.n;
+            std::lock_guard<std::mutex> lk2(mu);
+            st.resident = (int64_t)resident.size();
+            st.resident_bytes = bytes;
+        }
+        std::vector<Block> rest;
+        for (size_t b = 0; b < j.blocks.size(); ++b)
+            if (!kept[b]) rest.push_back(j.blocks[b]);
+        j.blocks.swap(rest);
     }
     release_blocks(j);
     stream_jobs[j.stream]--;
@@ -291,9 +419,11 @@ void dpm_server::run() {
             Job j;
             if (small(pending.front())) {
                 j.batched = true;
-                // continuous batching: every waiting small request, in arrival order
+                // continuous batching: every waiting small request of the same order as the
+                // first, in arrival order (a batch runs at one order)
+                const int kb = pending.front().r.max_order;
                 for (auto it = pending.begin(); it != pending.end() && (int)j.reqs.size() < cfg.batch_max;) {
-                    if (small(*it)) {
+                    if (small(*it) && it->r.max_order == kb) {
                         j.reqs.push_back(*it);
                         it = pending.erase(it);
                     } else {
@@ -305,7 +435,14 @@ void dpm_server::run() {
                 pending.pop_front();
             }
             for (auto &q : j.reqs) j.K = std::max(j.K, q.r.max_order);
-            if (!reserve(j)) {
+            bool ok = reserve(j);
+            while (!ok) {
+                // make room: drop resident 2D moments, least recently used first
+                release_blocks(j);
+                if (!evict_one()) break;
+                ok = reserve(j);
+            }
+            if (!ok) {
                 // does not fit now: put the group back at the front, in order
                 release_blocks(j);
                 for (auto it = j.reqs.rbegin(); it != j.reqs.rend(); ++it) pending.push_front(*it);
@@ -317,7 +454,13 @@ void dpm_server::run() {
                 pending.pop_front();
                 one.K = one.reqs[0].r.max_order;
                 one.batched = small(one.reqs[0]);
-                if (!reserve(one)) {
+                bool ok1 = reserve(one);
+                while (!ok1) {
+                    release_blocks(one);
+                    if (!evict_one()) break;
+                    ok1 = reserve(one);
+                }
+                if (!ok1) {
                     release_blocks(one);
                     stream_jobs[one.stream]++;  // finish() releases one job of its stream
                     finish(one, DPM_ENOMEM);
@@ -380,15 +523,22 @@ int dpm_server_create(const dpm_server_config *cfg, dpm_server **out) {
         ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;  // default priority
         if (ok) s->streams.push_back(st);
     }
+    ok = ok && hipStreamCreateWithFlags(&s->qstream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipHostMalloc(reinterpret_cast<void **>(&s->qhost), kQueryOut, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipMalloc(reinterpret_cast<void **>(&s->qdev), kQueryPart + kQueryOut) == hipSuccess;
     // warm every stream before serving: its first dispatch binds it to a hardware queue,
     // which would otherwise delay the first requests by milliseconds
     for (size_t i = 0; ok && i < s->streams.size(); ++i)
         ok = hipMemsetAsync(s->dev, 0, 256, s->streams[i]) == hipSuccess && hipStreamSynchronize(s->streams[i]) == hipSuccess;
+    ok = ok && hipMemsetAsync(s->dev, 0, 256, s->qstream) == hipSuccess && hipStreamSynchronize(s->qstream) == hipSuccess;
     (void)hipSetDevice(cur);
     if (!ok) {
         for (auto st : s->streams) (void)hipStreamDestroy(st);
+        if (s->qstream) (void)hipStreamDestroy(s->qstream);
         if (s->dev) (void)hipFree(s->dev);
         if (s->pin) (void)hipHostFree(s->pin);
+        if (s->qhost) (void)hipHostFree(s->qhost);
+        if (s->qdev) (void)hipFree(s->qdev);
         delete s;
         return DPM_ENOMEM;
     }
@@ -419,7 +569,8 @@ int dpm_server_submit(dpm_server *s, const dpm_request *req) {
     // refuse what can never fit: its own blocks exceed the whole arena
     const size_t ws = dpm_workspace_bytes(req->dims, (dpm_dtype)req->dtype, req->max_order);
     if (!ws) return DPM_ERANGE;
-    const size_t need = al(ws) + al(req->data_on_device ? 0 : q.bytes()) + al(16 * 1024);
+    const size_t need = al(ws) + al(req->data_on_device ? 0 : q.bytes()) + al(16 * 1024) +
+                        (req->keep_resident ? al(resident_bytes(req->max_order, 12)) : 0);
     if (need > (size_t)s->cfg.hbm_budget) return DPM_ERANGE;
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -459,6 +610,64 @@ int dpm_server_replay(dpm_server *s, const dpm_request *reqs, int n) {
     return DPM_OK;
 }
 
+int dpm_server_requery(dpm_server *s, uint64_t tag, int max_order, dpm_i128 *exact, double *fp64) {
+    if (!s || max_order < 0 || max_order > dpm::KMAX) return DPM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->res_mu);
+    auto it = s->resident.find(tag);
+    if (it == s->resident.end() || max_order > it->second.K) return DPM_EINVAL;
+    Resident &r = it->second;
+    r.tick = ++s->res_tick;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (hipSetDevice(s->cfg.device) != hipSuccess) return DPM_EDEVICE;
+    int rc = dpm::batched_ensure_tables();
+    const int K = max_order, nm = dpm::n_moments(K), nm4 = dpm::n_moments(std::min(K, 4));
+    uint8_t *qpart = s->qdev, *qout = qpart + kQueryPart;
+    const uint32_t *part = reinterpret_cast<const uint32_t *>(s->dev + r.off);
+    hipError_t e = hipSuccess;
+    if (!rc && K < r.K) {
+        // the recombination reads tiles laid out for its own order: re-stride first
+        e = dpm::launch_restride(part, r.K, reinterpret_cast<uint32_t *>(qpart), K, r.nlr, s->qstream);
+        part = reinterpret_cast<const uint32_t *>(qpart);
+    }
+    if (!rc && e == hipSuccess) {
+        // one tile per image side: tile s holds slot s (Section 3.2 recombination)
+        dpm::FinishArgs f{};
+        f.part = part;
+        f.rois = nullptr;
+        f.nvol = 1;
+        f.K = K;
+        for (int sl = 0; sl <= dpm::NSLOT; ++sl) f.tile0[sl] = std::min(sl, 2 * (K + 1));
+        f.exact = qout;
+        f.fp64 = reinterpret_cast<double *>(qout + 35 * 16);
+        f.raw = nullptr;
+        e = dpm::launch_finish(r.nlr, f, s->qstream);
+    }
+    if (!rc && e == hipSuccess) e = hipMemcpyAsync(s->qhost, qout, kQueryOut, hipMemcpyDeviceToHost, s->qstream);
+    if (!rc && e == hipSuccess) e = hipStreamSynchronize(s->qstream);
+    (void)hipSetDevice(cur);
+    if (rc) return rc;
+    if (e != hipSuccess) return DPM_EDEVICE;
+    if (exact) std::memcpy(exact, s->qhost, (size_t)nm4 * 16);
+    if (fp64) std::memcpy(fp64, s->qhost + 35 * 16, (size_t)nm * 8);
+    return DPM_OK;
+}
+
+int dpm_server_release(dpm_server *s, uint64_t tag) {
+    if (!s) return DPM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->res_mu);
+    auto it = s->resident.find(tag);
+    if (it == s->resident.end()) return DPM_EINVAL;
+    s->darena->release(it->second.off, it->second.n);
+    s->resident.erase(it);
+    int64_t b = 0;
+    for (auto &kv : s->resident) b += (int64_t)kv.second.n;
+    std::lock_guard<std::mutex> lk2(s->mu);
+    s->st.resident = (int64_t)s->resident.size();
+    s->st.resident_bytes = b;
+    return DPM_OK;
+}
+
 int dpm_server_stats_get(dpm_server *s, dpm_server_stats *out) {
     if (!s || !out) return DPM_EINVAL;
     std::lock_guard<std::mutex> lk(s->mu);
@@ -480,8 +689,11 @@ int dpm_server_destroy(dpm_server *s) {
     (void)hipSetDevice(s->cfg.device);
     for (auto st : s->streams)
         if (hipStreamDestroy(st) != hipSuccess) rc = DPM_EDEVICE;
+    if (s->qstream && hipStreamDestroy(s->qstream) != hipSuccess) rc = DPM_EDEVICE;
     if (s->dev && hipFree(s->dev) != hipSuccess) rc = DPM_EDEVICE;
     if (s->pin && hipHostFree(s->pin) != hipSuccess) rc = DPM_EDEVICE;
+    if (s->qhost && hipHostFree(s->qhost) != hipSuccess) rc = DPM_EDEVICE;
+    if (s->qdev && hipFree(s->qdev) != hipSuccess) rc = DPM_EDEVICE;
     (void)hipSetDevice(cur);
     delete s->darena;
     delete s->parena;

@@ -153,3 +153,119 @@ def test_server_serves_unbatchable_small_request_alone(dpm):
     assert done[tw]["status"] == 0 and done[tw]["batched"]
     assert_moments_equal(done[tv]["moments"], oracle.moments_exact(V, 6), 6, "column")
     assert_moments_equal(done[tw]["moments"], oracle.moments_exact(W, 6), 6, "cube")
+
+
+def test_server_requery_from_resident_image_moments(dpm):
+    """Requests kept resident answer later queries of any order up to theirs from their
+    image moments on the device, equal to the oracle; batched and single requests."""
+    say("server requery")
+    small = synth.sphere_mask((30, 26, 34), np.random.default_rng(3))
+    large = synth.mri_phantom((72, 64, 80), seed=4)
+    srv = dpm.Server(hbm_budget=1 << 30, n_streams=2, batch_voxels=40 ** 3)
+    try:
+        ts = srv.submit(to_dev(small), 6, keep=True)
+        tl = srv.submit(to_dev(large), 9, keep=True)
+        tn = srv.submit(to_dev(small), 6)  # not kept
+        done = {c["tag"]: c for c in drain(srv, 3)}
+        assert done[ts]["batched"] and not done[tl]["batched"]
+        st = srv.stats()
+        assert st["resident"] == 2 and st["resident_bytes"] > 0
+        for tag, V, K in [(ts, small, 6), (tl, large, 9)]:
+            ref = oracle.moments_exact(V, K)
+            for k in sorted({0, 1, 4, K // 2, K}):
+                got = srv.requery(tag, k)
+                assert_moments_equal(got, ref[:dpm.num_moments(k)], k, f"requery tag {tag} K={k}")
+        with pytest.raises(dpm.DpmError):
+            srv.requery(tn, 6)      # never kept
+        with pytest.raises(dpm.DpmError):
+            srv.requery(ts, 7)      # above the kept order
+        srv.release_resident(ts)
+        with pytest.raises(dpm.DpmError):
+            srv.requery(ts, 2)
+        assert srv.stats()["resident"] == 1
+    finally:
+        srv.close()
+
+
+def test_server_evicts_resident_entries_under_budget_pressure(dpm):
+    """A budget that holds one job and a few resident entries: later requests evict the
+    least recently used entries; every request still completes exactly, the entries that
+    remain still answer queries, and the evicted ones refuse them."""
+    say("server eviction")
+    shape = (48, 40, 56)
+    vols = [synth.uniform_volume(shape, np.uint16, seed=10 + s) for s in range(10)]
+    K = 6
+    ws = dpm.workspace_bytes(shape, 2, K)
+    # one job at a time (workspace, outputs, its resident block of about 11 KB) plus room
+    # for a few more resident entries
+    budget = ws + (64 << 10)
+    srv = dpm.Server(hbm_budget=budget, n_streams=1, batch_voxels=0, batch_max=1)
+    try:
+        tags = []
+        for V in vols:
+            tags.append(srv.submit(to_dev(V), K, keep=True))
+            drain(srv, 1)  # one after another: the oldest entries are the least recently used
+        st = srv.stats()
+        assert st["evictions"] > 0 and st["arena_peak_used"] <= budget
+        alive = [t for t in tags if t in _resident_tags(srv, tags, K)]
+        assert tags[-1] in alive and tags[0] not in alive
+        for t in alive:
+            V = vols[tags.index(t)]
+            assert_moments_equal(srv.requery(t, K), oracle.moments_exact(V, K), K, f"resident {t}")
+    finally:
+        srv.close()
+
+
+def _resident_tags(srv, tags, K):
+    import paper_2012_08099_amd as dpm
+    out = []
+    for t in tags:
+        try:
+            srv.requery(t, 0)
+            out.append(t)
+        except dpm.DpmError:
+            pass
+    return out
+
+
+def test_server_batches_only_requests_of_one_order(dpm):
+    """Small requests of different orders, waiting together, are served in batches of one
+    order each; every result is exact at its own order."""
+    say("server equal-order batches")
+    rng = np.random.default_rng(11)
+    reqs = [(synth.sphere_mask(tuple(int(s) for s in rng.integers(8, 30, size=3)), rng), int(k))
+            for k in rng.integers(0, 7, size=40)]
+    srv = dpm.Server(hbm_budget=1 << 28, n_streams=1, batch_voxels=32 ** 3, batch_max=64)
+    try:
+        tags = {srv.submit(to_dev(V), K): (V, K) for V, K in reqs}
+        done = drain(srv, len(reqs))
+        st = srv.stats()
+    finally:
+        srv.close()
+    assert st["batched_jobs"] >= len({K for _, K in reqs})
+    for c in done:
+        V, K = tags[c["tag"]]
+        assert c["status"] == 0 and c["batched"]
+        assert_moments_equal(c["moments"], oracle.moments_exact(V, K), K, f"order {K}")
+
+
+def test_server_waits_for_the_kernel_that_writes_a_device_input(dpm):
+    """A device volume written by a torch kernel just before submit (no synchronisation):
+    the request carries an event of torch's stream, and the result is that of the
+    written volume."""
+    import torch
+    say("server ready event")
+    V = synth.uniform_volume((64, 64, 96), np.uint16, seed=21)
+    src = to_dev(V)
+    srv = dpm.Server(hbm_budget=1 << 30, n_streams=2, batch_voxels=0)
+    try:
+        tags = {}
+        for i in range(4):
+            dst = torch.flip(src, dims=[2]) if i % 2 else torch.roll(src, shifts=5 * i + 1, dims=0)
+            ref = np.flip(V, axis=2) if i % 2 else np.roll(V, 5 * i + 1, axis=0)
+            tags[srv.submit(dst, 6)] = np.ascontiguousarray(ref)
+        done = drain(srv, 4)
+    finally:
+        srv.close()
+    for c in done:
+        assert_moments_equal(c["moments"], oracle.moments_exact(tags[c["tag"]], 6), 6, "flipped/rolled input")
