@@ -269,3 +269,32 @@ def test_server_waits_for_the_kernel_that_writes_a_device_input(dpm):
         srv.close()
     for c in done:
         assert_moments_equal(c["moments"], oracle.moments_exact(tags[c["tag"]], 6), 6, "flipped/rolled input")
+
+
+def test_server_at_the_served_mix_sizes(dpm):
+    """Requests of the served mix's own sizes: uint8 sphere ROIs of 32-128 per side,
+    uint16 256 x 256 x Z slabs and the 512^3 uint16 CT-like volume, order 6, inputs on the
+    device and in host memory, all in one server: every result equals the exact direct
+    sums of eq. (2) (the C oracle)."""
+    import torch
+    import oracle.native as onative
+    say("server at mix sizes")
+    rng = np.random.default_rng(31)
+    vols = [synth.sphere_mask((128, 96, 120), rng), synth.sphere_mask((32, 40, 64), rng),
+            synth.mri_phantom((160, 256, 256), seed=2), synth.mri_phantom((300, 256, 256), seed=3),
+            synth.ct_phantom((512, 512, 512), seed=1)]
+    refs = [onative.moments_hoisted(V, 6) for V in vols]
+    srv = dpm.Server(hbm_budget=4 << 30, n_streams=3, batch_voxels=128 ** 3)
+    try:
+        tags = {}
+        for i, V in enumerate(vols):
+            host = torch.from_numpy(V.view(np.int16) if V.dtype == np.uint16 else V)
+            for on_dev in (True, False):
+                tags[srv.submit(to_dev(V) if on_dev else host, 6)] = i
+        done = drain(srv, len(tags), timeout_ms=120000)
+    finally:
+        srv.close()
+    for c in done:
+        i = tags[c["tag"]]
+        assert c["status"] == 0
+        assert_moments_equal(c["moments"], refs[i], 6, f"mix size {vols[i].shape}")
