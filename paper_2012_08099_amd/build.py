@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libdpm.so")
 SOURCES = [
     "slice_g0_u16_fast.hip", "slice_g0_u16_gen.hip", "slice_g0_u8_fast.hip", "slice_g0_u8_gen.hip",
     "slice_g12_u16.hip", "slice_g12_u8.hip", "slice_groups_u16.hip", "slice_groups_u8.hip",
-    "slice_batched.hip", "power_kernels.hip", "features.hip", "from_images.hip",
+    "slice_batched.hip", "slice_block_u8.hip", "slice_block_u16.hip", "power_kernels.hip", "features.hip", "from_images.hip",
     "moment_kernels.hip", "noalloc.hip", "paper_mode.hip", "paper_api.cpp", "resident.hip", "slice_dispatch.cpp", "dpm_api.cpp", "batched.cpp", "server.cpp",
 ]
 ARCH = "gfx950"

@@ -47,12 +47,28 @@ struct BPlan {
     size_t lds = 0;
     bool has_u8 = false, has_u16 = false;
     bool mfma = false;
+    // fused kernel: one workgroup per (ROI, block of 16 slices), rows kept in LDS; LDS of
+    // each launch class (uint8 / uint16 row values, uint8 / uint32, uint16 / uint32)
+    bool fused = false;
+    size_t lds_block[3] = {0, 0, 0};
     int amax = 64;
     std::vector<RoiDesc> rd;
     size_t off_rd = 0, off_it = 0, off_geom = 0, off_rows = 0, off_part = 0, off_tmap = 0, total = 0;
 };
 
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+// The fused kernel takes a batch whose every ROI's block fits this much LDS (two
+// workgroups per CU at the limit); DPM_BATCH_FUSED=0 keeps the separate kernels.
+constexpr int64_t kBlockLdsMax = 80 * 1024;
+// Slices are grouped per wave while a ROI's block stays within the larger of this and
+// the batch's largest block at one slice per wave.
+constexpr int64_t kBlockLdsGroup = 48 * 1024;
+bool fused_allowed() {
+    const char *e = std::getenv("DPM_BATCH_FUSED");
+    return !(e && e[0] == '0');
+}
+int block_class(int elem, int rowbytes) { return elem == 2 ? 2 : rowbytes == 2 ? 0 : 1; }
 
 // Pinned staging for the descriptor upload, so the call stays asynchronous: a buffer
 // is reused only once the event recorded after its copy has fired.
@@ -91,6 +107,8 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     bool small_p = true;
     int64_t row_base = 0;
     int item0 = 0, tile0 = 0;
+    int64_t lds_blk_max = 0;
+    std::vector<ItemGeom> geoms(n);
     std::vector<std::pair<int64_t, int>> order;  // (cost, roi)
     for (int i = 0; i < n; ++i) {
         const dpm_roi &r = rois[i];
@@ -130,9 +148,14 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
                 brec = std::max(brec, bvol + k * bu + q * by + batched_numsum_bits(k) + 2);
         if ((double)vmax * (double)std::max(d.L, d.N) >= 268435456.0) small_p = false;
         // geometry of this ROI's items (full z range): LDS and row layout
-        ItemGeom ig;
+        ItemGeom &ig = geoms[i];
         item_geometry(0, nd, G, d.L, d.N, 0, d.N, ig);
         p.lds = std::max(p.lds, (size_t)ig.lds_dwords * 4);
+        // row values of the fused kernel: uint16 for uint8 voxels when no line sum can reach
+        // 2^16, else uint32 (the only instantiation for uint16 voxels)
+        d.rowbytes = elem == 1 && (double)vmax * (double)std::max(d.L, d.N) < 65536.0 ? 2 : 4;
+        d.spw = 1;
+        lds_blk_max = std::max(lds_blk_max, bk_lds_bytes(ig, nd, d.rowbytes, 1));
         int32_t off = 0, nsl = 0;
         for (int sl = 0; sl < 14; ++sl) {
             int32_t len = 0;
@@ -162,12 +185,31 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     if (p.lds > 160 * 1024) return DPM_ERANGE;
     int32_t cs[KMAX + 2];
     p.mfma = small_p && p.amax <= 8192 && batched_pow_columns(p.amax, K, cs);
+    p.fused = p.mfma && p.nlr == 4 && lds_blk_max <= kBlockLdsMax && fused_allowed();
+    if (p.fused) {
+        // work items are (ROI, block of 16 slices); no row buffer
+        item0 = 0;
+        const int64_t cap = std::max<int64_t>(lds_blk_max, kBlockLdsGroup);
+        for (int i = 0; i < n; ++i) {
+            RoiDesc &d = p.rd[i];
+            d.nitems = (int32_t)((d.M + BK_YB - 1) / BK_YB);
+            item0 += d.nitems;
+            // slices a wave projects together: enough units for two per sub-row, as far as
+            // the LDS of the batch's largest block allows
+            const int64_t u1 = (int64_t)d.CT * geoms[i].n_chunks, subrows = 64 / d.R;
+            while (d.spw < 4 && d.spw * u1 < 2 * subrows && bk_lds_bytes(geoms[i], nd, d.rowbytes, 2 * d.spw) <= cap)
+                d.spw *= 2;
+            size_t &cl = p.lds_block[block_class(d.elem, d.rowbytes)];
+            cl = std::max(cl, (size_t)bk_lds_bytes(geoms[i], nd, d.rowbytes, d.spw));
+        }
+        row_base = 0;
+    }
     // projection work items, largest slices first (LPT order)
     std::stable_sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
     int32_t pos = 0;
     for (auto &o : order) {
         p.rd[o.second].item_pos = pos;
-        pos += (int32_t)p.rd[o.second].M;
+        pos += p.rd[o.second].nitems;
     }
     p.items = item0;
     p.off_rd = 0;
@@ -192,10 +234,28 @@ hipError_t enqueue(const BPlan &p, const PowTab &pt, const uint8_t *packed, RoiD
     if (marks) batched_prof_mark(0, st);
     BatchSliceArgs a{packed, drd, dit, K, rows, tmap, reinterpret_cast<ItemGeom *>(ws + p.off_geom)};
     hipError_t e = launch_batched_prep(nd, a, p.nrois, st);
-    if (e == hipSuccess && p.has_u16) e = launch_slice_batched(2, 0, nd, a, p.items, p.lds, st);
-    if (e == hipSuccess && p.has_u8) e = launch_slice_batched(1, 0, nd, a, p.items, p.lds, st);
-    if (e == hipSuccess && marks) batched_prof_mark(1, st);
-    if (e == hipSuccess) {
+    if (p.fused) {
+        BlockArgs ba{};
+        ba.b = a;
+        ba.pw.rois = drd;
+        ba.pw.tile_roi = tmap;
+        ba.pw.nrois = p.nrois;
+        ba.pw.K = K;
+        ba.pw.ntiles = p.ntiles;
+        ba.pw.max_len = p.amax;
+        ba.pw.pow = pt;
+        ba.pw.part = part;
+        // one launch per class present; workgroups of the other classes return at once
+        const int elems[3] = {1, 1, 2}, rbytes[3] = {2, 4, 4};
+        for (int c = 0; c < 3 && e == hipSuccess; ++c)
+            if (p.lds_block[c]) e = launch_slice_block(elems[c], rbytes[c], nd, ba, p.items, p.lds_block[c], st);
+        if (e == hipSuccess && marks) batched_prof_mark(1, st);
+        if (e == hipSuccess && marks) batched_prof_mark(2, st);
+    }
+    if (!p.fused && e == hipSuccess && p.has_u16) e = launch_slice_batched(2, 0, nd, a, p.items, p.lds, st);
+    if (!p.fused && e == hipSuccess && p.has_u8) e = launch_slice_batched(1, 0, nd, a, p.items, p.lds, st);
+    if (!p.fused && e == hipSuccess && marks) batched_prof_mark(1, st);
+    if (!p.fused && e == hipSuccess) {
         PowerArgs pa{};
         pa.rows = rows;
         pa.rois = drd;
@@ -209,8 +269,8 @@ hipError_t enqueue(const BPlan &p, const PowTab &pt, const uint8_t *packed, RoiD
         pa.pow = pt;
         pa.part = part;
         e = launch_power(p.nls, p.nlr, pa, st);
+        if (e == hipSuccess && marks) batched_prof_mark(2, st);
     }
-    if (e == hipSuccess && marks) batched_prof_mark(2, st);
     if (e == hipSuccess) {
         FinishArgs f{};
         f.part = part;

@@ -186,6 +186,36 @@ DPM_HD void item_geometry(int g, int nd, int G, int64_t L, int64_t N, int64_t zs
     ig.lds_dwords = off + LDS_SINK;
 }
 
+// Fused batched kernel (one workgroup per (ROI, block of BK_YB y-slices)): LDS holds
+//   store:   for every non-empty slot s, BK_YB rows of bk_plen(s) row values (2 or 4
+//            bytes each) at a stride of bk_rstride() values (16 bytes more than a row,
+//            so the 16 rows of a matrix-core tile fall in different banks), slot after
+//            slot, 16-byte aligned in total;
+//   scratch: BK_WAVES regions of bk_scratch_dwords() dwords, one per wave: the
+//            projection's row accumulators of the spw slices the wave projects
+//            together (bk_slice_dwords() each), later the wave's 4 x 256 limb-pair table.
+constexpr int BK_WAVES = 4;
+constexpr int BK_YB = 16;
+constexpr int BK_SCR_MIN = 1024;
+// values per slice of slot s: the side's extent 0 .. ahi rounded up to 16 (0 if empty)
+DPM_HD int32_t bk_plen(const ItemGeom &ig, int s) {
+    return ig.seg_ahi[s] >= ig.seg_alo[s] ? (ig.seg_ahi[s] + 16) / 16 * 16 : 0;
+}
+DPM_HD int32_t bk_rstride(int32_t plen, int rowbytes) { return plen ? plen + 16 / rowbytes : 0; }
+DPM_HD int32_t bk_store_bytes(const ItemGeom &ig, int nd, int rowbytes) {
+    int32_t tot = 0;
+    for (int s = 0; s < 2 * nd; ++s) tot += BK_YB * bk_rstride(bk_plen(ig, s), rowbytes);
+    return (tot * rowbytes + 15) / 16 * 16;
+}
+DPM_HD int32_t bk_slice_dwords(const ItemGeom &ig) { return (ig.lds_dwords + 3) / 4 * 4; }
+DPM_HD int32_t bk_scratch_dwords(const ItemGeom &ig, int spw) {
+    const int32_t w = spw * bk_slice_dwords(ig);
+    return w > BK_SCR_MIN ? w : BK_SCR_MIN;
+}
+DPM_HD int64_t bk_lds_bytes(const ItemGeom &ig, int nd, int rowbytes, int spw) {
+    return (int64_t)bk_store_bytes(ig, nd, rowbytes) + (int64_t)BK_WAVES * bk_scratch_dwords(ig, spw) * 4;
+}
+
 // Row storage of the power-sum input: segment slot s of every item holds `len` int32
 // values for a = 0 .. len-1 (zero outside the item's [alo, ahi]); len is a multiple of
 // 64 and equal for all items of a launch.

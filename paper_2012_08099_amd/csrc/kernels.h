@@ -66,9 +66,11 @@ struct RoiDesc {
     int32_t row_stride;        // int32 values per item
     int32_t slot_off[14];      // orders <= 6: slots 0..13
     int32_t slot_len[14];
+    int32_t rowbytes;          // fused kernel: bytes of a row value in LDS (2 or 4)
+    int32_t spw;               // fused kernel: slices a wave projects together (1, 2 or 4)
 };
 
-struct BatchItem {              // one y-slice of one ROI, whole z range
+struct BatchItem {              // one y-slice of one ROI, whole z range (fused kernel: y = block of 16 slices)
     int32_t roi;
     int32_t y;
 };
@@ -117,6 +119,16 @@ hipError_t launch_batched_prep(int nd, const BatchSliceArgs &a, int nrois, hipSt
 hipError_t launch_slice_groups(int elem, int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st);
 hipError_t launch_slice_batched(int elem, int g, int nd, const BatchSliceArgs &a, int items, size_t lds,
                                 hipStream_t st);
+// Fused batched kernel: one workgroup per (ROI, block of 16 y-slices) projects the block's
+// slices into LDS and takes their matrix-core power sums from there, writing the same tile
+// partials as launch_power (pw: K, power table, part).  Workgroups of ROIs whose voxel
+// size or row-value size differs from (elem, rowbytes) return at once.
+struct BlockArgs {
+    BatchSliceArgs b;
+    PowerArgs pw;
+};
+hipError_t launch_slice_block(int elem, int rowbytes, int nd, const BlockArgs &a, int items, size_t lds,
+                              hipStream_t st);
 
 // Tile sums and recombination into the 3D moments; grid = (moments, volumes).
 struct FinishArgs {

@@ -14,6 +14,7 @@
 //  odd part's inverse).
 #include "dpm_common.h"
 #include "kernels.h"
+#include "lane_sum.h"
 #include "mw.h"
 
 namespace dpm {
@@ -97,20 +98,14 @@ __global__ void __launch_bounds__(NT) finish_kernel(FinishArgs a) {
 #pragma unroll
         for (int b = 0; b < FIN_BATCH; ++b) mw::add(num, mw::mul_i64(v[b], c[b]));
     }
-#pragma unroll
-    for (int sh = 1; sh < 64; sh <<= 1) {
-        mw::Int<NLR> o;
-#pragma unroll
-        for (int l = 0; l < NLR; ++l) o.w[l] = (uint32_t)__shfl_xor((int)num.w[l], sh, 64);
-        mw::add(num, o);
-    }
+    wave_sum_last(num);  // the wave's total in its lane 63
     if (NT > 64) {
-        if ((tid & 63) == 0)
+        if ((tid & 63) == 63)
 #pragma unroll
             for (int l = 0; l < NLR; ++l) wsum[tid >> 6][l] = num.w[l];
         __syncthreads();
     }
-    if (tid != 0) return;
+    if (tid != 63) return;
     for (int w = 1; w < NT / 64; ++w) {
         mw::Int<NLR> o;
 #pragma unroll

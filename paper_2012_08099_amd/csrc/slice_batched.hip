@@ -25,7 +25,7 @@ __global__ void __launch_bounds__(64) batched_prep_kernel(BatchSliceArgs a, int 
         item_geometry(0, nd, lane_voxels(rd.elem), rd.L, rd.N, 0, rd.N, g);
         a.geom[roi] = g;
     }
-    for (int64_t y = threadIdx.x; y < rd.M; y += 64) a.items[rd.item_pos + y] = BatchItem{roi, (int32_t)y};
+    for (int32_t y = threadIdx.x; y < rd.nitems; y += 64) a.items[rd.item_pos + y] = BatchItem{roi, y};
     for (int64_t j = threadIdx.x; j < rd.ntiles; j += 64) a.tile_roi[rd.tile0 + j] = roi;
 }
 

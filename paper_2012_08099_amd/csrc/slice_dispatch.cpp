@@ -16,6 +16,15 @@ hipError_t launch_slice_g12_u8(int g, bool fast, int nd, const SliceArgs &a, int
 hipError_t launch_slice_groups_u16(int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st);
 hipError_t launch_slice_groups_u8(int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st);
 
+hipError_t launch_slice_block_u8(int rowbytes, int nd, const BlockArgs &a, int items, size_t lds, hipStream_t st);
+hipError_t launch_slice_block_u16(int nd, const BlockArgs &a, int items, size_t lds, hipStream_t st);
+
+hipError_t launch_slice_block(int elem, int rowbytes, int nd, const BlockArgs &a, int items, size_t lds,
+                              hipStream_t st) {
+    if (elem == 2) return rowbytes == 4 ? launch_slice_block_u16(nd, a, items, lds, st) : hipErrorInvalidValue;
+    return launch_slice_block_u8(rowbytes, nd, a, items, lds, st);
+}
+
 hipError_t launch_slice_groups(int elem, int nd, const SliceArgs &a, int items, size_t lds, hipStream_t st) {
     return elem == 2 ? launch_slice_groups_u16(nd, a, items, lds, st) : launch_slice_groups_u8(nd, a, items, lds, st);
 }

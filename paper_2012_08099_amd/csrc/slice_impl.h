@@ -170,21 +170,30 @@ struct GroupTraits {
 #define SLICE_UNITS_IN_FLIGHT 2
 #endif
 
-template <typename VT, int D0, int ND, bool FAST, int NW>
-__device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pitch_z, int64_t zs,
-                             int64_t ze, int R, int CT, uint32_t *lds, const ItemGeom &ig) {
+// MS: the item is nsl consecutive slices (slice s at slice + s pitch_y, its row
+// accumulators at lds + s sw), whose units the sub-rows share: small slices then keep
+// more of the wave busy.
+template <typename VT, int D0, int ND, bool FAST, int NW, bool MS = false>
+__device__ __forceinline__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pitch_z, int64_t zs,
+                             int64_t ze, int R, int CT, uint32_t *lds, const ItemGeom &ig, int nsl = 1,
+                             int64_t pitch_y = 0, int32_t sw = 0) {
     using Tr = GroupTraits<D0, ND>;
     using Vec = typename VecOf<VT>::type;
     constexpr int G = VecOf<VT>::G;
     constexpr int T = Tr::T;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // a one-wave item may run inside a larger workgroup (the fused batched kernel): its
+    // wave is then the only one of the item
+    const int wave = NW == 1 ? 0 : (int)(threadIdx.x >> 6);
     const int SR = 64 / R;
     const int sr = lane / R, r = lane % R;
     const int gsr = wave * SR + sr, NSR = NW * SR;
     const int64_t nch = ig.n_chunks;
-    const int64_t U = (int64_t)CT * nch;
-    const int64_t u_begin = (int64_t)gsr * U / NSR, u_end = (int64_t)(gsr + 1) * U / NSR;
+    const int64_t U1 = (int64_t)CT * nch;  // units of one slice
+    const int64_t U = MS ? U1 * nsl : U1;
+    // (multi-slice items are small: 32-bit unit arithmetic)
+    const int64_t u_begin = MS ? (int64_t)((uint32_t)(gsr * U) / (uint32_t)NSR) : (int64_t)gsr * U / NSR;
+    const int64_t u_end = MS ? (int64_t)((uint32_t)((gsr + 1) * U) / (uint32_t)NSR) : (int64_t)(gsr + 1) * U / NSR;
 
     uint32_t xy[G];
 #pragma unroll
@@ -199,18 +208,27 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
     });
     const int32_t yz_off = ig.yz_off, yz_stride = ig.yz_stride;
 
-    // unit u = ct * nch + ch: column tile ct, T-row chunk ch.  Positions advance by
-    // counters (no divisions in the loop); a unit's first row pointer is kept per lane.
+    // unit u = (sl * CT + ct) * nch + ch: slice sl (MS only), column tile ct, T-row chunk
+    // ch.  Positions advance by counters (no divisions in the loop); a unit's first row
+    // pointer is kept per lane.
     struct Pos {
-        int32_t ct, ch;
+        int32_t ct, ch, sl;
         const VT *p;  // row zs + ch * T of this lane's voxels
     };
     const int64_t chunk_step = (int64_t)T * pitch_z;
     auto pos_of = [&](int64_t u) {
         Pos q;
-        q.ct = (int32_t)(u / nch);
+        q.sl = 0;
+        if constexpr (MS) {
+            q.sl = (int32_t)((uint32_t)u / (uint32_t)U1);
+            u -= (int64_t)q.sl * U1;
+            q.ct = (int32_t)((uint32_t)u / (uint32_t)nch);
+        } else {
+            q.ct = (int32_t)(u / nch);
+        }
         q.ch = (int32_t)(u - (int64_t)q.ct * nch);
-        q.p = slice + (zs + (int64_t)q.ch * T) * pitch_z + ((int64_t)q.ct * 64 * G + (int64_t)r * G);
+        q.p = slice + (MS ? q.sl * pitch_y : 0) + (zs + (int64_t)q.ch * T) * pitch_z +
+              ((int64_t)q.ct * 64 * G + (int64_t)r * G);
         return q;
     };
     auto next_pos = [&](Pos q) {
@@ -219,7 +237,13 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
         if (q.ch == nch) {
             q.ch = 0;
             ++q.ct;
-            q.p = slice + zs * pitch_z + ((int64_t)q.ct * 64 * G + (int64_t)r * G);
+            if constexpr (MS) {
+                if (q.ct == CT) {
+                    q.ct = 0;
+                    ++q.sl;
+                }
+            }
+            q.p = slice + (MS ? q.sl * pitch_y : 0) + zs * pitch_z + ((int64_t)q.ct * 64 * G + (int64_t)r * G);
         }
         return q;
     };
@@ -235,12 +259,14 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
             } else {
                 const int64_t z = zc0 + t;
                 const bool in = valid && z < ze;
-                buf[t] = load_lane<VT, false>(slice + (z < ze ? z : ze - 1) * pitch_z, x0, L, in);
+                buf[t] = load_lane<VT, false>(slice + (MS ? q.sl * pitch_y : 0) + (z < ze ? z : ze - 1) * pitch_z,
+                                              x0, L, in);
             }
         });
     };
 
     auto process_unit = [&](const Vec(&dat)[T], const Pos &q, bool last_in_tile) {
+        uint32_t *const ul = lds + (MS ? q.sl * sw : 0);  // this unit's slice's accumulators
         const int32_t x0 = q.ct * 64 * G + r * G;
         const bool valid = x0 < L;
         const int32_t zc0 = (int32_t)zs + q.ch * T;
@@ -281,7 +307,7 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
                     if constexpr (tt == TD - 1) {
                         if (FAST || valid) {
                             const uint32_t lb = (uint32_t)(rel0 + Bt * (t - (TD - 1)));
-                            uint32_t *base = lds + doff + (lb + lb / PP);
+                            uint32_t *base = ul + doff + (lb + lb / PP);
                             StaticFor<0, S>::run([&](auto sc) {
                                 constexpr int s = decltype(sc)::value;
                                 if constexpr (slot_used<d, G>(s)) atomicAdd(base + (s + s / PP), w[s]);
@@ -294,7 +320,7 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
 
         if constexpr (Tr::has_yz) {
             if ((lane & 7) == 0) {
-                uint32_t *base = lds + yz_off + ((lane >> 3) & (YZ_COPIES - 1)) * yz_stride +
+                uint32_t *base = ul + yz_off + ((lane >> 3) & (YZ_COPIES - 1)) * yz_stride +
                                  (uint32_t)(zc0 - zs);
                 StaticFor<0, T>::run([&](auto tc) {
                     constexpr int t = decltype(tc)::value;
@@ -302,12 +328,12 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
                 });
             }
         }
-        // XY: flush when the next unit of this sub-row is in another column tile
+        // XY: flush when the next unit of this sub-row is in another column tile (or slice)
         if constexpr (Tr::has_xy) {
             if (last_in_tile) {
                 if (FAST || valid) {
                     const uint32_t x0u = (uint32_t)x0;
-                    uint32_t *base = lds + coff[0] + (x0u + x0u / (uint32_t)dir_pp(0, G));
+                    uint32_t *base = ul + coff[0] + (x0u + x0u / (uint32_t)dir_pp(0, G));
                     StaticFor<0, G>::run([&](auto jc) {
                         constexpr int j = decltype(jc)::value;
                         atomicAdd(base + j, xy[j]);
@@ -341,7 +367,7 @@ __device__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pi
             if (u < n) {
                 pos[lj] = next_pos(pos[pj]);
                 if (u + NB - 1 < n) load_unit(buf[lj], pos[lj]);
-                process_unit(buf[j], pos[j], u + 1 >= n || pos[nj].ct != pos[j].ct);
+                process_unit(buf[j], pos[j], u + 1 >= n || pos[nj].ct != pos[j].ct || (MS && pos[nj].sl != pos[j].sl));
             }
         });
     }

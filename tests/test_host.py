@@ -212,6 +212,37 @@ def test_batched_workspace_rejects_bad_rois(lib):
     assert lib.dpm_batched_workspace_bytes(rois, 2, 7) == 0   # batched path: orders <= 6
 
 
+def _rois(shapes):
+    """ROI descriptors for (L, M, N, dtype) tuples, packed one after the other."""
+    from paper_2012_08099_amd import _lib
+    rois = (_lib.Roi * len(shapes))()
+    off = 0
+    for i, (L, M, N, dt) in enumerate(shapes):
+        rois[i].offset_bytes = off
+        rois[i].dims[:] = [L, M, N]
+        rois[i].dtype = dt
+        off += L * M * N * dt
+    return rois
+
+
+def test_batched_plan_takes_the_fused_kernel_when_blocks_fit(lib, monkeypatch):
+    """Small ROIs go to the fused kernel (rows kept in LDS: no row buffer in the
+    workspace); DPM_BATCH_FUSED=0 restores the separate kernels and their row buffer; a
+    batch with a block beyond the fused kernel's LDS keeps the separate kernels."""
+    small = _rois([(20, 33, 17, 1), (96, 96, 96, 1), (40, 5, 21, 2)])
+    monkeypatch.setenv("DPM_BATCH_FUSED", "1")
+    fused = lib.dpm_batched_workspace_bytes(small, 3, 4)
+    monkeypatch.setenv("DPM_BATCH_FUSED", "0")
+    separate = lib.dpm_batched_workspace_bytes(small, 3, 4)
+    # the separate kernels' row buffer: at least one int32 per voxel row of every slice
+    assert fused > 0 and separate - fused >= 4 * (33 * 17 + 96 * 96 + 5 * 21)
+    wide = _rois([(20, 33, 17, 1), (4000, 3, 9, 1)])  # one 4000-voxel row side per slice
+    monkeypatch.setenv("DPM_BATCH_FUSED", "1")
+    a = lib.dpm_batched_workspace_bytes(wide, 2, 6)
+    monkeypatch.setenv("DPM_BATCH_FUSED", "0")
+    assert a == lib.dpm_batched_workspace_bytes(wide, 2, 6) > 0
+
+
 def test_tuning_overrides_change_the_plan_only(lib):
     """dpm_tune_set: a per-shape override of the work split shows in dpm_plan (z-splits,
     power tiles) and is removed by t=NULL / dpm_tune_clear; bad values are refused."""
