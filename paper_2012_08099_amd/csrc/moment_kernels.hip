@@ -42,6 +42,29 @@ constexpr int FIN_THREADS = 256;   // one volume: up to 2 * 16 * (K+1) tiles per
 constexpr int FIN_THREADS_ROI = 64; // batched ROIs: a few tiles per moment, one wave
 constexpr int FIN_BATCH = 4;  // entries whose loads are in flight together
 
+// moment m of volume vol = num / den(k, p), by an exact division (den = 2^shift * odd:
+// arithmetic shift, then multiplication by the odd part's inverse mod 2^(32 NLR)), to the
+// outputs the caller asked for.
+template <int NLR>
+__device__ __forceinline__ void finish_store(const FinishArgs &a, int vol, int m, int k, int p, mw::Int<NLR> num) {
+    const int K = a.K;
+    mw::sar(num, c_shift[k][p]);
+    mw::Int<NLR> inv;
+#pragma unroll
+    for (int l = 0; l < NLR; ++l) inv.w[l] = c_inv[k][p][l];
+    const mw::Int<NLR> val = mw::mul_mod(num, inv);
+    const int nm = n_moments(K), nm4 = n_moments(K < 4 ? K : 4);
+    if (a.fp64) a.fp64[(size_t)vol * nm + m] = mw::to_double(val);
+    if (a.raw)
+#pragma unroll
+        for (int l = 0; l < NLR; ++l) a.raw[((size_t)vol * nm + m) * NLR + l] = val.w[l];
+    if (a.exact && m < nm4) {
+        uint64_t *e = reinterpret_cast<uint64_t *>(a.exact) + 2 * ((size_t)vol * nm4 + m);
+        e[0] = (uint64_t)val.w[0] | ((uint64_t)val.w[1] << 32);
+        e[1] = (uint64_t)val.w[2] | ((uint64_t)val.w[3] << 32);
+    }
+}
+
 template <int NLR, int NT>
 __global__ void __launch_bounds__(NT) finish_kernel(FinishArgs a) {
     __shared__ uint32_t wsum[NT / 64][NLR];
@@ -112,27 +135,57 @@ __global__ void __launch_bounds__(NT) finish_kernel(FinishArgs a) {
         for (int l = 0; l < NLR; ++l) o.w[l] = wsum[w][l];
         mw::add(num, o);
     }
-    // exact division by den = 2^shift * odd
-    mw::sar(num, c_shift[k][p]);
-    mw::Int<NLR> inv;
+    finish_store(a, vol, m, k, p, num);
+}
+
+// Recombination of batched ROIs: one workgroup per ROI, thread m computes moment m from
+// the ROI's few tiles on its own (no cross-lane sums), with the loads of FIN_BATCH tiles
+// in flight together.
+constexpr int FIN_ROI_THREADS = 128;  // >= n_moments(6) = 84
+
+template <int NLR>
+__global__ void __launch_bounds__(FIN_ROI_THREADS) finish_roi_kernel(FinishArgs a) {
+    const int vol = blockIdx.x, m = threadIdx.x, K = a.K;
+    if (m >= n_moments(K)) return;  // no barriers below
+    int p, q, r;
+    decode_moment(m, p, q, r);
+    const int k = p + r;
+    const RoiDesc &rd = a.rois[vol];
+    const int ipt = (int)((rd.M + 15) / 16);
+    mw::Int<NLR> num;
+    mw::set_zero(num);
+    int rank = 0;
+    for (int s = 0; s < 14 && s < 2 * (k + 1); ++s) {
+        if (!rd.slot_len[s]) continue;
+        const int d = s >> 1, side = s & 1;
+        const int64_t c = (side == 0 && (k & 1)) ? -c_num[k][p][d] : c_num[k][p][d];
+        const size_t t0 = (size_t)rd.tile0 + (size_t)rank * ipt;
+        ++rank;
+        if (c == 0) continue;
+        for (int b0 = 0; b0 < ipt; b0 += FIN_BATCH) {
+            mw::Int<NLR> v[FIN_BATCH];
 #pragma unroll
-    for (int l = 0; l < NLR; ++l) inv.w[l] = c_inv[k][p][l];
-    const mw::Int<NLR> val = mw::mul_mod(num, inv);
-    const int nm = n_moments(K), nm4 = n_moments(K < 4 ? K : 4);
-    if (a.fp64) a.fp64[(size_t)vol * nm + m] = mw::to_double(val);
-    if (a.raw)
+            for (int b = 0; b < FIN_BATCH; ++b) {
+                mw::set_zero(v[b]);
+                if (b0 + b < ipt) {
+                    const uint32_t *src = a.part + (((t0 + b0 + b) * (K + 1) + k) * (K + 1) + q) * NLR;
 #pragma unroll
-        for (int l = 0; l < NLR; ++l) a.raw[((size_t)vol * nm + m) * NLR + l] = val.w[l];
-    if (a.exact && m < nm4) {
-        uint64_t *e = reinterpret_cast<uint64_t *>(a.exact) + 2 * ((size_t)vol * nm4 + m);
-        e[0] = (uint64_t)val.w[0] | ((uint64_t)val.w[1] << 32);
-        e[1] = (uint64_t)val.w[2] | ((uint64_t)val.w[3] << 32);
+                    for (int l = 0; l < NLR; ++l) v[b].w[l] = src[l];
+                }
+            }
+            mw::Int<NLR> sv = v[0];
+#pragma unroll
+            for (int b = 1; b < FIN_BATCH; ++b) mw::add(sv, v[b]);
+            mw::add(num, mw::mul_i64(sv, c));
+        }
     }
+    finish_store(a, vol, m, k, p, num);
 }
 
 template <int NLR>
 static void finish_go(const FinishArgs &a, dim3 grid, hipStream_t st) {
-    if (a.rois) hipLaunchKernelGGL((finish_kernel<NLR, FIN_THREADS_ROI>), grid, dim3(FIN_THREADS_ROI), 0, st, a);
+    if (a.rois && a.K <= 6) hipLaunchKernelGGL((finish_roi_kernel<NLR>), dim3(a.nvol), dim3(FIN_ROI_THREADS), 0, st, a);
+    else if (a.rois) hipLaunchKernelGGL((finish_kernel<NLR, FIN_THREADS_ROI>), grid, dim3(FIN_THREADS_ROI), 0, st, a);
     else hipLaunchKernelGGL((finish_kernel<NLR, FIN_THREADS>), grid, dim3(FIN_THREADS), 0, st, a);
 }
 
