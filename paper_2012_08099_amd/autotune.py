@@ -51,13 +51,16 @@ def _key(shape, dtype_code, K):
 
 
 def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS, waves=WAVES, stream=None,
-         objective="latency", finalists=3, confirm_rounds=3):
+         objective="latency", finalists=3, confirm_rounds=3, margin=0.02):
     """Measure every (z_splits, power_chunk, waves) candidate on the device volume ``vol``
     ((N, M, L) uint8, or uint16 carried as int16) and install the fastest.
 
     One sweep of short timings is noisy, so the ``finalists`` fastest candidates and the
     planner's default (0, 0, 0) are timed again, ``confirm_rounds`` times each in turn with
-    twice the repetitions, and the one with the lowest median is installed.
+    twice the repetitions, and the one with the lowest median is installed -- unless it beats
+    the default by less than ``margin`` (a fraction of the default's time): then the
+    default stays, so that differences inside the timing noise do not flip the choice
+    from run to run.
 
     Returns {"best": {...}, "candidates": [{"z_splits", "power_chunk", "waves", "ms"}, ...],
     "confirmed": [{..., "ms": median of the confirmation rounds}, ...]}."""
@@ -119,6 +122,9 @@ def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS
     confirmed = [{"z_splits": c[0], "power_chunk": c[1], "waves": c[2], "ms": sorted(t)[len(t) // 2]}
                  for c, t in times.items()]
     best = min(confirmed, key=lambda r: r["ms"])
+    default = next((r for r in confirmed if trip(r) == (0, 0, 0)), None)
+    if default is not None and best["ms"] > default["ms"] * (1.0 - margin):
+        best = default
     set_tuning(shape, code, K, best["z_splits"], best["power_chunk"], best["waves"])
     return {"key": _key(shape, code, K), "best": best, "candidates": results, "confirmed": confirmed,
             "objective": objective}
