@@ -64,7 +64,9 @@ __global__ void __launch_bounds__(BK_WAVES * 64, bk_min_blocks<VT>()) slice_bloc
     constexpr int NS = 2 * ND;
     const BatchItem it = a.b.items[blockIdx.x];
     const RoiDesc &rd = a.b.rois[it.roi];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // the wave index as a scalar: what derives from it (scratch base, slice groups) stays
+    // in scalar registers
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     {
         // (its loads overlap those of the descriptor)
         const int32_t *src = reinterpret_cast<const int32_t *>(a.b.geom + it.roi);
@@ -103,7 +105,7 @@ __global__ void __launch_bounds__(BK_WAVES * 64, bk_min_blocks<VT>()) slice_bloc
         const int nsl = ny - j0 < spw ? ny - j0 : spw;
         for (int i = lane; i < nsl * SW / 4; i += 64) reinterpret_cast<uint4 *>(scr)[i] = make_uint4(0u, 0u, 0u, 0u);
         wave_lds_sync();
-        project_rows<VT, 0, ND, false, 1, true>(vol + (y0 + j0) * rd.L, rd.L, pitch_z, 0, rd.N, rd.R, rd.CT, scr, ig,
+        project_rows<VT, 0, ND, false, 1, true, 1>(vol + (y0 + j0) * rd.L, rd.L, pitch_z, 0, rd.N, rd.R, rd.CT, scr, ig,
                                                 nsl, rd.L, SW);
         wave_lds_sync();
         // row sides into the store: four values per lane, read together, one store

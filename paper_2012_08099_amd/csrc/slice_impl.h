@@ -173,7 +173,7 @@ struct GroupTraits {
 // MS: the item is nsl consecutive slices (slice s at slice + s pitch_y, its row
 // accumulators at lds + s sw), whose units the sub-rows share: small slices then keep
 // more of the wave busy.
-template <typename VT, int D0, int ND, bool FAST, int NW, bool MS = false>
+template <typename VT, int D0, int ND, bool FAST, int NW, bool MS = false, int NBU = SLICE_UNITS_IN_FLIGHT>
 __device__ __forceinline__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pitch_z, int64_t zs,
                              int64_t ze, int R, int CT, uint32_t *lds, const ItemGeom &ig, int nsl = 1,
                              int64_t pitch_y = 0, int32_t sw = 0) {
@@ -345,13 +345,25 @@ __device__ __forceinline__ void project_rows(const VT *__restrict__ slice, int64
         }
     };
 
-    // NB units in flight: the loads of unit u + NB - 1 are issued before unit u is summed
-    // (buffer u % NB; the position of unit u + 1 tells whether u ends its column tile)
-    constexpr int NB = SLICE_UNITS_IN_FLIGHT;
-    Vec buf[NB][T];
-    Pos pos[NB];
     if (u_begin >= u_end) return;
     const int32_t n = (int32_t)(u_end - u_begin);
+    if constexpr (NBU == 1) {
+        // one unit's loads at a time (fewer registers; the other waves hide the latency)
+        Vec one[T];
+        Pos q = pos_of(u_begin);
+        for (int32_t u = 0; u < n; ++u) {
+            load_unit(one, q);
+            const Pos nq = next_pos(q);
+            process_unit(one, q, u + 1 >= n || nq.ct != q.ct || (MS && nq.sl != q.sl));
+            q = nq;
+        }
+        return;
+    }
+    // NB units in flight: the loads of unit u + NB - 1 are issued before unit u is summed
+    // (buffer u % NB; the position of unit u + 1 tells whether u ends its column tile)
+    constexpr int NB = NBU;
+    Vec buf[NB][T];
+    Pos pos[NB];
     pos[0] = pos_of(u_begin);
     load_unit(buf[0], pos[0]);
     StaticFor<1, NB - 1>::run([&](auto ic) {
