@@ -194,6 +194,14 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
             RoiDesc &d = p.rd[i];
             d.nitems = (int32_t)((d.M + BK_YB - 1) / BK_YB);
             item0 += d.nitems;
+            // the fused kernel's sub-rows may be narrower than 8 lanes: rows of <= 32
+            // voxels keep their lanes busy
+            if (d.CT == 1) {
+                const int64_t lanes = (d.L + lane_voxels(d.elem) - 1) / lane_voxels(d.elem);
+                int rr = 1;
+                while (rr < lanes) rr <<= 1;
+                d.R = rr;
+            }
             // slices a wave projects together: enough units for two per sub-row, as far as
             // the LDS of the batch's largest block allows
             const int64_t u1 = (int64_t)d.CT * geoms[i].n_chunks, subrows = 64 / d.R;

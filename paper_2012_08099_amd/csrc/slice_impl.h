@@ -85,6 +85,15 @@ __device__ __forceinline__ uint32_t group8_sum(uint32_t s) {
     return s;
 }
 
+// Sum over each aligned group of gs lanes (gs = 1, 2, 4 or 8, uniform); every lane of the
+// group gets the total.
+__device__ __forceinline__ uint32_t group_sum(uint32_t s, int gs) {
+    if (gs >= 2) s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0xB1, 0xF, 0xF, false);
+    if (gs >= 4) s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x4E, 0xF, 0xF, false);
+    if (gs >= 8) s += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)s, 0x141, 0xF, 0xF, false);
+    return s;
+}
+
 // Is (tt, j) the first touch of its window slot within a block (t outer, j inner)?
 template <int D, int G>
 __device__ constexpr bool first_touch(int tt, int j) {
@@ -187,6 +196,10 @@ __device__ __forceinline__ void project_rows(const VT *__restrict__ slice, int64
     const int wave = NW == 1 ? 0 : (int)(threadIdx.x >> 6);
     const int SR = 64 / R;
     const int sr = lane / R, r = lane % R;
+    // (0,1) row sums over 8-lane groups; multi-slice items may have narrower sub-rows
+    // (R = 1, 2 or 4), whose sums then take the whole sub-row
+    int gs = 8;
+    if constexpr (MS) gs = R < 8 ? R : 8;
     const int gsr = wave * SR + sr, NSR = NW * SR;
     const int64_t nch = ig.n_chunks;
     const int64_t U1 = (int64_t)CT * nch;  // units of one slice
@@ -280,7 +293,10 @@ __device__ __forceinline__ void project_rows(const VT *__restrict__ slice, int64
                     xy[j] += voxel<VT>(v, j);
                 });
             }
-            if constexpr (Tr::has_yz) yzs[t] = group8_sum(lane_sum<VT>(v));
+            if constexpr (Tr::has_yz) {
+                if constexpr (MS) yzs[t] = group_sum(lane_sum<VT>(v), gs);
+                else yzs[t] = group8_sum(lane_sum<VT>(v));
+            }
         });
 
         // sheared directions: register windows, flushed every T_d rows
@@ -319,7 +335,9 @@ __device__ __forceinline__ void project_rows(const VT *__restrict__ slice, int64
         });
 
         if constexpr (Tr::has_yz) {
-            if ((lane & 7) == 0) {
+            bool writer = (lane & 7) == 0;
+            if constexpr (MS) writer = (lane & (gs - 1)) == 0;
+            if (writer) {
                 uint32_t *base = ul + yz_off + ((lane >> 3) & (YZ_COPIES - 1)) * yz_stride +
                                  (uint32_t)(zc0 - zs);
                 StaticFor<0, T>::run([&](auto tc) {
