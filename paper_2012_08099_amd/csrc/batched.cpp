@@ -52,6 +52,7 @@ struct BPlan {
     bool fused = false;
     size_t lds_block[3] = {0, 0, 0};
     int amax = 64;
+    int64_t packed_bytes = 0;  // end of the last byte of any ROI in the packed buffer
     std::vector<RoiDesc> rd;
     size_t off_rd = 0, off_it = 0, off_geom = 0, off_rows = 0, off_part = 0, off_tmap = 0, total = 0;
 };
@@ -123,6 +124,7 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
         d.M = r.dims[1];
         d.N = r.dims[2];
         d.elem = elem;
+        p.packed_bytes = std::max<int64_t>(p.packed_bytes, d.offset + d.L * d.M * d.N * elem);
         const int G = lane_voxels(elem);
         const int64_t lanes = (d.L + G - 1) / G;
         if (lanes <= 64) {
@@ -240,7 +242,8 @@ hipError_t enqueue(const BPlan &p, const PowTab &pt, const uint8_t *packed, RoiD
     uint32_t *part = reinterpret_cast<uint32_t *>(ws + p.off_part);
     int32_t *tmap = reinterpret_cast<int32_t *>(ws + p.off_tmap);
     if (marks) batched_prof_mark(0, st);
-    BatchSliceArgs a{packed, drd, dit, K, rows, tmap, reinterpret_cast<ItemGeom *>(ws + p.off_geom)};
+    BatchSliceArgs a{packed, drd, dit, K, rows, tmap, reinterpret_cast<ItemGeom *>(ws + p.off_geom),
+                     packed + p.packed_bytes};
     hipError_t e = launch_batched_prep(nd, a, p.nrois, st);
     if (p.fused) {
         BlockArgs ba{};

@@ -83,6 +83,7 @@ struct BatchSliceArgs {
     int32_t *rows;
     int32_t *tile_roi;         // written by the prep kernel: ROI of every power-sum tile
     ItemGeom *geom;            // written by the prep kernel: geometry of every ROI
+    const uint8_t *packed_end; // end of the ROIs' bytes in the packed buffer (readable before it)
 };
 
 // Power sums of the image rows, weighted in y per tile of 16 items:

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(BK_WAVES * 64, bk_min_blocks<VT>()) slice_bloc
         for (int i = lane; i < nsl * SW / 4; i += 64) reinterpret_cast<uint4 *>(scr)[i] = make_uint4(0u, 0u, 0u, 0u);
         wave_lds_sync();
         project_rows<VT, 0, ND, false, 1, true, 1>(vol + (y0 + j0) * rd.L, rd.L, pitch_z, 0, rd.N, rd.R, rd.CT, scr, ig,
-                                                nsl, rd.L, SW);
+                                                nsl, rd.L, SW, a.b.packed_end);
         wave_lds_sync();
         // row sides into the store: four values per lane, read together, one store
         StaticFor<0, ND>::run([&](auto ic) {

@@ -118,8 +118,11 @@ __device__ constexpr bool slot_used(int s) {
     return false;
 }
 
+// safe_end (general loads only, may be null): every byte before it may be read, so a lane
+// whose dwords all lie before it loads them without a check per dword
 template <typename VT, bool FAST>
-__device__ __forceinline__ typename VecOf<VT>::type load_lane(const VT *row, int64_t x0, int64_t L, bool in) {
+__device__ __forceinline__ typename VecOf<VT>::type load_lane(const VT *row, int64_t x0, int64_t L, bool in,
+                                                              const uint8_t *safe_end = nullptr) {
     using Vec = typename VecOf<VT>::type;
     using Raw = typename VecOf<VT>::raw;
     constexpr int G = VecOf<VT>::G;
@@ -141,9 +144,14 @@ __device__ __forceinline__ typename VecOf<VT>::type load_lane(const VT *row, int
         const uint32_t *dw = reinterpret_cast<const uint32_t *>(a0 & ~(uintptr_t)3);
         const uint32_t sh = (uint32_t)(a0 & 3);
         uint32_t d[NDW];
+        if (safe_end && reinterpret_cast<const uint8_t *>(dw + NDW) <= safe_end) {
 #pragma unroll
-        for (int k = 0; k < NDW; ++k)
-            d[k] = (reinterpret_cast<uintptr_t>(dw + k) <= last) ? dw[k] : 0u;
+            for (int k = 0; k < NDW; ++k) d[k] = dw[k];  // bytes past the row are cleared below
+        } else {
+#pragma unroll
+            for (int k = 0; k < NDW; ++k)
+                d[k] = (reinterpret_cast<uintptr_t>(dw + k) <= last) ? dw[k] : 0u;
+        }
         const int nbv = (int)(nv * (int64_t)sizeof(VT));
         uint32_t w[NB / 4];
 #pragma unroll
@@ -185,7 +193,7 @@ struct GroupTraits {
 template <typename VT, int D0, int ND, bool FAST, int NW, bool MS = false, int NBU = SLICE_UNITS_IN_FLIGHT>
 __device__ __forceinline__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pitch_z, int64_t zs,
                              int64_t ze, int R, int CT, uint32_t *lds, const ItemGeom &ig, int nsl = 1,
-                             int64_t pitch_y = 0, int32_t sw = 0) {
+                             int64_t pitch_y = 0, int32_t sw = 0, const uint8_t *safe_end = nullptr) {
     using Tr = GroupTraits<D0, ND>;
     using Vec = typename VecOf<VT>::type;
     constexpr int G = VecOf<VT>::G;
@@ -273,7 +281,7 @@ __device__ __forceinline__ void project_rows(const VT *__restrict__ slice, int64
                 const int64_t z = zc0 + t;
                 const bool in = valid && z < ze;
                 buf[t] = load_lane<VT, false>(slice + (MS ? q.sl * pitch_y : 0) + (z < ze ? z : ze - 1) * pitch_z,
-                                              x0, L, in);
+                                              x0, L, in, MS ? safe_end : nullptr);
             }
         });
     };
