@@ -243,13 +243,13 @@ typedef struct {
 size_t dpm_batched_workspace_bytes(const dpm_roi *rois, int n_rois, int max_order);
 
 /* All ROIs in one launch sequence on `stream`: a prep kernel (per-ROI geometry and
- * work items); one fused kernel in which a workgroup projects a block of 16 y-slices of
+ * work items); a fused kernel in which a workgroup projects a block of 16 y-slices of
  * one ROI (Section 3.1, eq. 4) and takes the exact power sums of the block's image rows
- * without writing them to memory (when every ROI's block fits the fused kernel's LDS,
- * about 80 KB, and the exact sums fit 128 bits; else, or with DPM_BATCH_FUSED=0 in the
- * environment, a projection kernel per (ROI, y) slice that writes the rows and a
- * power-sum kernel over them); one recombination per (ROI, moment) (Section 3.2).
- * Both ways give the same integers.  Orders <= 6 (else DPM_ENOTSUP); ROI
+ * without writing them to memory, for every ROI whose block fits its LDS (about 80 KB)
+ * when the exact sums fit 128 bits; for the other ROIs (all of them with
+ * DPM_BATCH_FUSED=0 in the environment) a projection kernel per (ROI, y) slice that
+ * writes the rows and a power-sum kernel over them; one recombination per ROI
+ * (Section 3.2).  Both ways give the same integers.  Orders <= 6 (else DPM_ENOTSUP); ROI
  * dims <= 4096, and every ROI's image rows over its whole z range must fit the LDS of
  * one workgroup (160 KB; e.g. a 1 x 1 x 4096 column at order 6 does not), else
  * DPM_ERANGE -- dpm_batched_workspace_bytes then returns 0; such a volume goes through

@@ -45,11 +45,14 @@ struct BPlan {
     int K = 0, nrois = 0, items = 0, npairs = 0, ntiles = 0;
     int nls = 4, nlr = 4;
     size_t lds = 0;
-    bool has_u8 = false, has_u16 = false;
     bool mfma = false;
-    // fused kernel: one workgroup per (ROI, block of 16 slices), rows kept in LDS; LDS of
-    // each launch class (uint8 / uint16 row values, uint8 / uint32, uint16 / uint32)
-    bool fused = false;
+    // ROIs whose block of 16 slices fits the fused kernel go to it (rows kept in LDS), the
+    // others to the separate projection and power-sum kernels.  Their work items and tiles
+    // come first: items [0, items_sep), tiles [0, ntiles_sep); the fused ROIs' blocks and
+    // tiles follow.  LDS of each fused launch class (uint8 / uint16 row values, uint8 /
+    // uint32, uint16 / uint32).
+    int n_fused = 0, items_sep = 0, ntiles_sep = 0;
+    bool sep_u8 = false, sep_u16 = false;
     size_t lds_block[3] = {0, 0, 0};
     int amax = 64;
     int64_t packed_bytes = 0;  // end of the last byte of any ROI in the packed buffer
@@ -106,17 +109,15 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     const int nd = K + 1;
     int brec = 0, bsl = 0;
     bool small_p = true;
-    int64_t row_base = 0;
-    int item0 = 0, tile0 = 0;
-    int64_t lds_blk_max = 0;
     std::vector<ItemGeom> geoms(n);
+    std::vector<int64_t> lds1(n);   // fused block at one slice per wave
+    std::vector<int32_t> nslot(n);  // non-empty slots
     std::vector<std::pair<int64_t, int>> order;  // (cost, roi)
     for (int i = 0; i < n; ++i) {
         const dpm_roi &r = rois[i];
         const int elem = r.dtype == DPM_U8 ? 1 : r.dtype == DPM_U16 ? 2 : 0;
         if (!elem || r.dims[0] <= 0 || r.dims[1] <= 0 || r.dims[2] <= 0) return DPM_EINVAL;
         if (r.dims[0] > 4096 || r.dims[1] > 4096 || r.dims[2] > 4096) return DPM_ERANGE;
-        (elem == 1 ? p.has_u8 : p.has_u16) = true;
         RoiDesc &d = p.rd[i];
         d = RoiDesc{};
         d.offset = (int64_t)r.offset_bytes;
@@ -157,7 +158,7 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
         // 2^16, else uint32 (the only instantiation for uint16 voxels)
         d.rowbytes = elem == 1 && (double)vmax * (double)std::max(d.L, d.N) < 65536.0 ? 2 : 4;
         d.spw = 1;
-        lds_blk_max = std::max(lds_blk_max, bk_lds_bytes(ig, nd, d.rowbytes, 1));
+        lds1[i] = bk_lds_bytes(ig, nd, d.rowbytes, 1);
         int32_t off = 0, nsl = 0;
         for (int sl = 0; sl < 14; ++sl) {
             int32_t len = 0;
@@ -169,16 +170,9 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
             p.amax = std::max(p.amax, (int)len);
         }
         d.row_stride = off;
-        d.row_base = row_base;
-        row_base += (int64_t)off * d.M;
-        d.nitems = (int32_t)d.M;
-        item0 += (int32_t)d.M;
-        d.tile0 = tile0;
-        d.ntiles = nsl * (int)((d.M + 15) / 16);
-        tile0 += d.ntiles;
+        nslot[i] = nsl;
         order.push_back({d.L * d.N, i});
     }
-    p.ntiles = tile0;
     if (bsl > 128) return DPM_ERANGE;
     p.nls = 4;
     if (brec <= 128) p.nlr = 4;
@@ -187,15 +181,41 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     if (p.lds > 160 * 1024) return DPM_ERANGE;
     int32_t cs[KMAX + 2];
     p.mfma = small_p && p.amax <= 8192 && batched_pow_columns(p.amax, K, cs);
-    p.fused = p.mfma && p.nlr == 4 && lds_blk_max <= kBlockLdsMax && fused_allowed();
-    if (p.fused) {
-        // work items are (ROI, block of 16 slices); no row buffer
-        item0 = 0;
+    const bool fuse_ok = p.mfma && p.nlr == 4 && fused_allowed();
+    std::vector<char> fz(n, 0);
+    int64_t lds_blk_max = 0;
+    for (int i = 0; i < n; ++i)
+        if (fuse_ok && lds1[i] <= kBlockLdsMax) {
+            fz[i] = 1;
+            ++p.n_fused;
+            lds_blk_max = std::max(lds_blk_max, lds1[i]);
+        }
+    // separate ROIs: one work item per slice, rows in the workspace, their tiles first
+    int64_t row_base = 0;
+    int32_t tile0 = 0;
+    for (int i = 0; i < n; ++i) {
+        if (fz[i]) continue;
+        RoiDesc &d = p.rd[i];
+        d.row_base = row_base;
+        row_base += (int64_t)d.row_stride * d.M;
+        d.nitems = (int32_t)d.M;
+        p.items_sep += d.nitems;
+        d.tile0 = tile0;
+        d.ntiles = nslot[i] * (int)((d.M + 15) / 16);
+        tile0 += d.ntiles;
+        (d.elem == 1 ? p.sep_u8 : p.sep_u16) = true;
+    }
+    p.ntiles_sep = tile0;
+    if (p.n_fused) {
+        // fused ROIs: work items (ROI, block of 16 slices), no rows
         const int64_t cap = std::max<int64_t>(lds_blk_max, kBlockLdsGroup);
         for (int i = 0; i < n; ++i) {
+            if (!fz[i]) continue;
             RoiDesc &d = p.rd[i];
             d.nitems = (int32_t)((d.M + BK_YB - 1) / BK_YB);
-            item0 += d.nitems;
+            d.tile0 = tile0;
+            d.ntiles = nslot[i] * (int)((d.M + 15) / 16);
+            tile0 += d.ntiles;
             // the fused kernel's sub-rows may be narrower than 8 lanes: rows of <= 32
             // voxels keep their lanes busy
             if (d.CT == 1) {
@@ -212,16 +232,18 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
             size_t &cl = p.lds_block[block_class(d.elem, d.rowbytes)];
             cl = std::max(cl, (size_t)bk_lds_bytes(geoms[i], nd, d.rowbytes, d.spw));
         }
-        row_base = 0;
     }
-    // projection work items, largest slices first (LPT order)
+    p.ntiles = tile0;
+    // work items of each kind, largest slices first (LPT order)
     std::stable_sort(order.begin(), order.end(), [](auto &a, auto &b) { return a.first > b.first; });
-    int32_t pos = 0;
+    int32_t pos_s = 0, pos_f = p.items_sep;
     for (auto &o : order) {
-        p.rd[o.second].item_pos = pos;
-        pos += p.rd[o.second].nitems;
+        RoiDesc &d = p.rd[o.second];
+        int32_t &pos = fz[o.second] ? pos_f : pos_s;
+        d.item_pos = pos;
+        pos += d.nitems;
     }
-    p.items = item0;
+    p.items = pos_f;
     p.off_rd = 0;
     p.off_it = al(sizeof(RoiDesc) * n);
     p.off_geom = p.off_it + al(sizeof(BatchItem) * (size_t)p.items);
@@ -245,9 +267,10 @@ hipError_t enqueue(const BPlan &p, const PowTab &pt, const uint8_t *packed, RoiD
     BatchSliceArgs a{packed, drd, dit, K, rows, tmap, reinterpret_cast<ItemGeom *>(ws + p.off_geom),
                      packed + p.packed_bytes};
     hipError_t e = launch_batched_prep(nd, a, p.nrois, st);
-    if (p.fused) {
+    if (e == hipSuccess && p.n_fused) {
         BlockArgs ba{};
         ba.b = a;
+        ba.b.items = dit + p.items_sep;  // the fused ROIs' blocks
         ba.pw.rois = drd;
         ba.pw.tile_roi = tmap;
         ba.pw.nrois = p.nrois;
@@ -259,29 +282,28 @@ hipError_t enqueue(const BPlan &p, const PowTab &pt, const uint8_t *packed, RoiD
         // one launch per class present; workgroups of the other classes return at once
         const int elems[3] = {1, 1, 2}, rbytes[3] = {2, 4, 4};
         for (int c = 0; c < 3 && e == hipSuccess; ++c)
-            if (p.lds_block[c]) e = launch_slice_block(elems[c], rbytes[c], nd, ba, p.items, p.lds_block[c], st);
-        if (e == hipSuccess && marks) batched_prof_mark(1, st);
-        if (e == hipSuccess && marks) batched_prof_mark(2, st);
+            if (p.lds_block[c])
+                e = launch_slice_block(elems[c], rbytes[c], nd, ba, p.items - p.items_sep, p.lds_block[c], st);
     }
-    if (!p.fused && e == hipSuccess && p.has_u16) e = launch_slice_batched(2, 0, nd, a, p.items, p.lds, st);
-    if (!p.fused && e == hipSuccess && p.has_u8) e = launch_slice_batched(1, 0, nd, a, p.items, p.lds, st);
-    if (!p.fused && e == hipSuccess && marks) batched_prof_mark(1, st);
-    if (!p.fused && e == hipSuccess) {
+    if (e == hipSuccess && p.sep_u16) e = launch_slice_batched(2, 0, nd, a, p.items_sep, p.lds, st);
+    if (e == hipSuccess && p.sep_u8) e = launch_slice_batched(1, 0, nd, a, p.items_sep, p.lds, st);
+    if (e == hipSuccess && marks) batched_prof_mark(1, st);
+    if (e == hipSuccess && p.ntiles_sep) {
         PowerArgs pa{};
         pa.rows = rows;
         pa.rois = drd;
         pa.tile_roi = tmap;
         pa.nrois = p.nrois;
-        pa.nitems = p.items;
+        pa.nitems = p.items_sep;
         pa.zsplits = 1;
         pa.K = K;
-        pa.ntiles = p.ntiles;
+        pa.ntiles = p.ntiles_sep;  // the separate ROIs' tiles
         pa.max_len = p.amax;
         pa.pow = pt;
         pa.part = part;
         e = launch_power(p.nls, p.nlr, pa, st);
-        if (e == hipSuccess && marks) batched_prof_mark(2, st);
     }
+    if (e == hipSuccess && marks) batched_prof_mark(2, st);
     if (e == hipSuccess) {
         FinishArgs f{};
         f.part = part;

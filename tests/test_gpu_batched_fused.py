@@ -101,3 +101,13 @@ def test_fused_uint16_order4(dpm, monkeypatch):
 def test_fused_roi_batch_1000(dpm, monkeypatch):
     """The bench's batch: 1000 uint8 sphere ROIs U{8..96}^3 at order 4."""
     check(dpm, synth.roi_batch(1000, seed=1), 4, monkeypatch, "1000 ROIs")
+
+
+def test_fused_and_separate_rois_in_one_batch(dpm, monkeypatch):
+    """ROIs whose block fits the fused kernel take it, the others (a 128^3 sphere and a
+    long uint16 column at order 6) the separate kernels, in one call."""
+    rng = np.random.default_rng(12)
+    rois = [synth.sphere_mask((128, 128, 128), rng), synth.sphere_mask((40, 33, 50), rng),
+            synth.uniform_volume((3, 70, 2), np.uint16, seed=4), synth.uniform_volume((900, 2, 3), np.uint16, seed=5),
+            synth.sphere_mask((20, 17, 90), rng)]
+    check(dpm, rois, 6, monkeypatch, "mixed fused / separate")

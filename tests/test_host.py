@@ -227,8 +227,9 @@ def _rois(shapes):
 
 def test_batched_plan_takes_the_fused_kernel_when_blocks_fit(lib, monkeypatch):
     """Small ROIs go to the fused kernel (rows kept in LDS: no row buffer in the
-    workspace); DPM_BATCH_FUSED=0 restores the separate kernels and their row buffer; a
-    batch with a block beyond the fused kernel's LDS keeps the separate kernels."""
+    workspace); DPM_BATCH_FUSED=0 restores the separate kernels and their row buffer; in a
+    batch with a block beyond the fused kernel's LDS, only that ROI keeps the separate
+    kernels and its rows."""
     small = _rois([(20, 33, 17, 1), (96, 96, 96, 1), (40, 5, 21, 2)])
     monkeypatch.setenv("DPM_BATCH_FUSED", "1")
     fused = lib.dpm_batched_workspace_bytes(small, 3, 4)
@@ -237,10 +238,14 @@ def test_batched_plan_takes_the_fused_kernel_when_blocks_fit(lib, monkeypatch):
     # the separate kernels' row buffer: at least one int32 per voxel row of every slice
     assert fused > 0 and separate - fused >= 4 * (33 * 17 + 96 * 96 + 5 * 21)
     wide = _rois([(20, 33, 17, 1), (4000, 3, 9, 1)])  # one 4000-voxel row side per slice
+    alone = _rois([(4000, 3, 9, 1)])
     monkeypatch.setenv("DPM_BATCH_FUSED", "1")
-    a = lib.dpm_batched_workspace_bytes(wide, 2, 6)
+    a, w1 = lib.dpm_batched_workspace_bytes(wide, 2, 6), lib.dpm_batched_workspace_bytes(alone, 1, 6)
     monkeypatch.setenv("DPM_BATCH_FUSED", "0")
-    assert a == lib.dpm_batched_workspace_bytes(wide, 2, 6) > 0
+    b, w0 = lib.dpm_batched_workspace_bytes(wide, 2, 6), lib.dpm_batched_workspace_bytes(alone, 1, 6)
+    assert w1 == w0 > 0                       # the wide ROI alone: separate kernels either way
+    assert 0 < a < b                           # the small one drops its rows in the mixed batch
+    assert b - a >= 4 * 33 * 17                # at least one int32 per voxel row of its slices
 
 
 def test_tuning_overrides_change_the_plan_only(lib):
