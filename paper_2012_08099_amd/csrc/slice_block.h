@@ -24,11 +24,9 @@
 namespace dpm {
 
 // Workgroups per CU the register budget is cut for (the block store and scratch of the
-// batches this kernel takes leave room for about three; the uint16 projection needs
-// more registers than a third of the file), and 16-column tiles of powers per pass of
-// the contraction.
-template <typename VT>
-constexpr int bk_min_blocks() { return sizeof(VT) == 1 ? 3 : 2; }
+// batches this kernel takes leave room for about three), and 16-column tiles of powers
+// per pass of the contraction.
+constexpr int BK_MIN_BLOCKS = 3;
 constexpr int BK_NTP = 2;
 
 // Orders this wave's LDS accesses before and after (all lanes of the wave).
@@ -56,7 +54,7 @@ __device__ __forceinline__ void split_limbs16(const uint32_t (&p)[8], v4i (&A)[4
 }
 
 template <typename VT, int ND, typename RV>
-__global__ void __launch_bounds__(BK_WAVES * 64, bk_min_blocks<VT>()) slice_block_kernel(BlockArgs a) {
+__global__ void __launch_bounds__(BK_WAVES * 64, BK_MIN_BLOCKS) slice_block_kernel(BlockArgs a) {
     extern __shared__ uint4 lds_raw[];
     __shared__ ItemGeom ig;
     __shared__ int32_t plen[MAXSEG], soff[MAXSEG], rstr[MAXSEG], tot_s;  // block store: values, first value, stride
