@@ -111,3 +111,22 @@ def test_fused_and_separate_rois_in_one_batch(dpm, monkeypatch):
             synth.uniform_volume((3, 70, 2), np.uint16, seed=4), synth.uniform_volume((900, 2, 3), np.uint16, seed=5),
             synth.sphere_mask((20, 17, 90), rng)]
     check(dpm, rois, 6, monkeypatch, "mixed fused / separate")
+
+
+@pytest.mark.parametrize("K", [0, 2, 4, 5, 6])
+def test_fused_random_shapes(dpm, monkeypatch, K):
+    """60 seeded random ROIs per order: dims 1-130 (rows of 1-8, 9-32, 33-64 and wider
+    voxels, single slices, ragged blocks), both voxel types, uniform random or sphere
+    contents; some blocks fit the fused kernel and some (large ones) do not."""
+    rng = np.random.default_rng(100 + K)
+    rois = []
+    for i in range(60):
+        dims = tuple(int(v) for v in rng.integers(1, 131, size=3))
+        if rng.random() < 0.3:
+            dims = (dims[0], dims[1], int(rng.integers(1, 9)))  # very short rows
+        dt = np.uint8 if rng.random() < 0.7 else np.uint16
+        if dt == np.uint8 and min(dims) >= 8 and rng.random() < 0.5:
+            rois.append(synth.sphere_mask(dims, rng))
+        else:
+            rois.append(synth.uniform_volume(dims, dt, seed=int(rng.integers(1 << 30))))
+    check(dpm, rois, K, monkeypatch, f"random shapes K={K}")
