@@ -42,10 +42,12 @@ __host__ __device__ constexpr int lane_voxels(int elem) { return 8; }
 // (conflict-free) except for alpha = 2 with G = 8, which stays two-way so that its
 // window blocks stay 8 rows long.
 __host__ __device__ constexpr int dir_pp(int d, int G) { return (G == 4 && dir_alpha(d) == 2) ? 8 : G; }
-// Rows per window block: the smallest T with beta*T = 0 mod PP, so every block base
-// is PP-aligned relative to the row origin and flush offsets are compile-time.
+// Rows per window block: a multiple T of PP / gcd(beta, PP), so that beta*T = 0 mod PP,
+// every block base is PP-aligned relative to the row origin and flush offsets are
+// compile-time -- here the whole unit of group_rows() = 8 rows (PP = 8), so a window is
+// flushed once per unit.
 __host__ __device__ constexpr int dir_td(int d, int G) {
-    return dir_beta(d) == 0 ? 1 : dir_pp(d, G) / gcd_c(iabs_c(dir_beta(d)), dir_pp(d, G));
+    return dir_beta(d) == 0 ? 1 : 8;
 }
 // Window slots of one lane per block: alpha (G-1) + |beta| (T_d - 1) + 1.
 __host__ __device__ constexpr int dir_slots(int d, int G) {
@@ -62,6 +64,7 @@ __host__ __device__ constexpr int group_begin(int g) { return g == 0 ? 0 : g == 
 __host__ __device__ constexpr int group_end(int g) { return g == 0 ? 7 : g == 1 ? 12 : 17; }
 // Rows per chunk (unit of work and of double buffering): a multiple of every T_d.
 __host__ __device__ constexpr int group_rows(int g) { return 8; }
+static_assert(group_rows(0) == 8 && dir_pp(0, 8) == 8, "window blocks are one unit of 8 rows");
 // Copies of the (0,1) row accumulator: 8-lane groups g and g+4 of a wave share copy g % 4.
 constexpr int YZ_COPIES = 4;
 // Dwords after the row accumulators that absorb the (0,1) adds of the lanes that hold
