@@ -13,7 +13,7 @@
 //     power-sum kernel: r(y, s, k) = sum_a a^k row(y, s, a) from 7-bit limbs of the row
 //     values (A operand, read from LDS) and of a^k (B operand, the power table), the
 //     limb-pair sums reassembled exactly; then T(tile, k, q) = sum_y y^q r(y, s, k).
-//     Wave w takes the slots of rank w, w + 4, ... among the non-empty ones.
+//     Each slot goes to the least loaded wave, longest first.
 // The tile partials land where the power-sum kernel puts them (tile = tile0 of the ROI +
 // rank of the slot x blocks of the ROI + block), so recombination is unchanged; the rows
 // never leave LDS.
@@ -144,16 +144,23 @@ __global__ void __launch_bounds__(BK_WAVES * 64, BK_MIN_BLOCKS) slice_block_kern
     const bool iv = il < ny;
     const uint4 *bt = pa.pow.b + lane;
     constexpr int NJ = epi_nj<64>();
+    // slots to waves, longest first onto the least loaded wave (the same arithmetic in every
+    // wave): cost = (k, q) pairs of the y-weighting + 2 per K-step of the contraction
+    int load[BK_WAVES] = {};
     int rank = 0;
     for (int s = 0; s < NS; ++s) {
         if (plen[s] == 0) continue;
-        const int my = (rank % BK_WAVES) == wave;
-        const int tile = rd.tile0 + rank * ipt + it.y;
-        ++rank;
-        if (!my) continue;
         const int d = s >> 1;
         const int32_t len = plen[s];
         const int nks = (len + 63) / 64;
+        int wl = 0;
+#pragma unroll
+        for (int w = 1; w < BK_WAVES; ++w)
+            if (load[w] < load[wl]) wl = w;
+        load[wl] += (pa.K + 1 - d) * (pa.K + 2 - d) / 2 + 2 * nks;
+        const int tile = rd.tile0 + rank * ipt + it.y;
+        ++rank;
+        if (wl != wave) continue;
         const RV *rowp = store + soff[s] + il * rstr[s] + g4 * 16;
         mw::Int<4> R[NJ];
 #pragma unroll
