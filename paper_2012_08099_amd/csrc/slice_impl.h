@@ -180,11 +180,13 @@ struct GroupTraits {
 };
 
 // ------------------------------------------------------------ step 1: projection
-// Units (T rows of a lane's voxels) whose loads are in flight per wave.  The workgroup
-// count, not the register file, bounds the occupancy of the projection, so the buffers
-// can be deep.
+// Units (T rows of a lane's voxels) whose loads are in flight per wave.  One: the load
+// buffers then hold few registers (about 110 instead of 200 for the uint16 first group),
+// so more waves share a CU -- eight-wave workgroups, or the power sums and recombination of
+// another volume on a second stream -- which hides the load latency better than a second
+// buffer in each wave.
 #ifndef SLICE_UNITS_IN_FLIGHT
-#define SLICE_UNITS_IN_FLIGHT 2
+#define SLICE_UNITS_IN_FLIGHT 1
 #endif
 
 // MS: the item is nsl consecutive slices (slice s at slice + s pitch_y, its row
