@@ -434,7 +434,7 @@ int dpm_plan(const int64_t dims[3], dpm_dtype dtype, int max_order, dpm_plan_inf
  *   power_chunk: steps of 64 values of a per power-sum tile on the matrix cores;
  *                0 = the planner's choice, -1 = whole rows.
  *   waves:       waves per projection workgroup of the first direction group when
- *                whole rows are loaded: 0 = the planner's choice (4), 4 or 8.
+ *                whole rows are loaded: 0 = the planner's choice (8), 4 or 8.
  * An override applies to every later plan of exactly these dims, dtype and order, and
  * to the workspace size reported for them (query dpm_workspace_bytes after setting
  * it).  The environment overrides DPM_ZSPLITS / DPM_PW_KCHUNK take precedence.

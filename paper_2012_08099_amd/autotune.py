@@ -7,7 +7,7 @@ Three planner choices change how one volume's work is divided, never its result:
 * ``power_chunk``: steps of 64 coordinates per power-sum tile on the matrix cores (smaller
   chunks mean more, shorter workgroups and more tile partials to combine);
 * ``waves``: waves per projection workgroup (first direction group, whole-row loads): 8
-  helps when there are too few slices to fill the CUs.
+  by default, which keeps more loads in flight per CU; 4 halves the LDS per workgroup.
 
 ``tune`` times every candidate triple with ``dpm_moments_async`` (HIP events around ``reps``
 calls: on one stream for the "latency" objective, alternating over two streams with a
@@ -28,7 +28,7 @@ from . import _dims_of_shape, _dtype_code, check, lib, moments_async, num_moment
 
 Z_SPLITS = (0, 1, 2, 4, 8)        # 0: the planner's choice
 POWER_CHUNKS = (0, 4, 8, 16, -1)  # 0: the planner's choice, -1: whole rows
-WAVES = (0, 8)                    # 0: the planner's choice (4)
+WAVES = (0, 4)                    # 0: the planner's choice (8 where whole rows are loaded)
 
 
 def set_tuning(shape, dtype_code, K, z_splits=0, power_chunk=0, waves=0):

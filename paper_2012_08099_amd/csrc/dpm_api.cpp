@@ -359,7 +359,7 @@ int make_plan(const int64_t dims[3], dpm_dtype dtype, int K, bool full_rows, Pla
         if (best > 160 * 1024) return DPM_ERANGE;
     }
     p.one_launch = p.fast && p.ngroups > 1;
-    p.waves = (p.fast && p.tune.waves == 8) ? 8 : 4;
+    p.waves = (p.fast && p.tune.waves != 4) ? 8 : 4;
     if (const char *e = std::getenv("DPM_SLICE_WAVES")) {
         if (atoi(e) == 8 && p.fast) p.waves = 8;
         if (atoi(e) == 4) p.waves = 4;

@@ -103,8 +103,9 @@ PATH_OVERRIDES = [
     ({"DPM_ZSPLITS": "4", "DPM_NO_MFMA": "1"}, (70, 5, 64), np.uint8, 5),
     ({"DPM_FORCE_GENERIC": "1"}, (32, 8, 128), np.uint16, 6),
     ({"DPM_GROUP_LAUNCHES": "1"}, (32, 8, 128), np.uint16, 16),  # one launch per direction group
-    ({"DPM_SLICE_WAVES": "8"}, (32, 5, 512), np.uint16, 6),      # 8 waves per projection workgroup
-    ({"DPM_SLICE_WAVES": "8"}, (48, 6, 256), np.uint8, 4),
+    ({"DPM_SLICE_WAVES": "4"}, (32, 5, 512), np.uint16, 6),      # 4 waves per projection workgroup
+    ({"DPM_SLICE_WAVES": "4"}, (48, 6, 256), np.uint8, 4),
+    ({"DPM_SLICE_WAVES": "4", "DPM_ZSPLITS": "2"}, (64, 3, 128), np.uint16, 5),
     ({"DPM_SLICE_WAVES": "8", "DPM_ZSPLITS": "2"}, (64, 3, 128), np.uint16, 5),
     ({"DPM_GROUP_LAUNCHES": "1"}, (48, 5, 64), np.uint8, 9),
     # chained-window projection (opt-in): rows of whole 64-lane tiles, 32-row units

@@ -23,7 +23,7 @@ def test_autotune_installs_an_exact_split():
     V = synth.uniform_volume((64, 48, 96), np.uint16, seed=2)
     vol = to_dev(V)
     try:
-        r = autotune.tune(vol, 6, reps=3, warmup=1, z_splits=(0, 1, 2, 4), power_chunks=(0, 4, -1), waves=(0, 8),
+        r = autotune.tune(vol, 6, reps=3, warmup=1, z_splits=(0, 1, 2, 4), power_chunks=(0, 4, -1), waves=(0, 4),
                           objective="throughput")
         assert len(r["candidates"]) == 24 and all(c["ms"] > 0 for c in r["candidates"])
         best = r["best"]
@@ -38,7 +38,7 @@ def test_autotune_installs_an_exact_split():
         assert r2["objective"] == "latency" and len(r2["candidates"]) == 2
         assert_moments_equal(dpm.moments(vol, 6), oracle.moments_exact(V, 6), 6, f"tuned {r2['best']}")
         # no candidate beats the default by the whole default time: the default stays
-        r3 = autotune.tune(vol, 6, reps=2, warmup=1, z_splits=(0, 2), power_chunks=(0, 4), waves=(0, 8), margin=1.0)
+        r3 = autotune.tune(vol, 6, reps=2, warmup=1, z_splits=(0, 2), power_chunks=(0, 4), waves=(0, 4), margin=1.0)
         assert (r3["best"]["z_splits"], r3["best"]["power_chunk"], r3["best"]["waves"]) == (0, 0, 0)
     finally:
         autotune.clear()

@@ -277,11 +277,13 @@ def test_tuning_overrides_change_the_plan_only(lib):
     assert plan(lib, dims, 2, 6)[1].z_splits == base.z_splits
     # waves per projection workgroup: whole-row shapes only
     fast = (128, 64, 256)
+    assert plan(lib, fast, 2, 6)[1].proj_waves == 8
+    assert lib.dpm_tune_set(d3(*fast), 2, 6, ctypes.byref(_lib.Tuning(0, 0, 4))) == 0
     assert plan(lib, fast, 2, 6)[1].proj_waves == 4
     assert lib.dpm_tune_set(d3(*fast), 2, 6, ctypes.byref(_lib.Tuning(0, 0, 8))) == 0
     assert plan(lib, fast, 2, 6)[1].proj_waves == 8
     assert lib.dpm_tune_set(d3(*fast), 2, 6, None) == 0
-    assert plan(lib, fast, 2, 6)[1].proj_waves == 4
+    assert plan(lib, fast, 2, 6)[1].proj_waves == 8
     for bad in (_lib.Tuning(-1, 0), _lib.Tuning(5000, 0), _lib.Tuning(1, -2), _lib.Tuning(1, 5000),
                 _lib.Tuning(1, 0, 5)):
         assert lib.dpm_tune_set(d3(*dims), 2, 6, ctypes.byref(bad)) == -1
