@@ -89,6 +89,7 @@ __global__ void __launch_bounds__(BK_WAVES * 64, BK_MIN_BLOCKS) slice_block_kern
     RV *store = reinterpret_cast<RV *>(lds_raw);
     const int32_t sbytes = (tot * (int32_t)sizeof(RV) + 15) / 16 * 16;
     const int spw = rd.spw;
+    if (spw < 1 || spw > 4) return;  // uniform; the planner takes 1, 2 or 4 (the row-side copy assumes <= 4)
     const int32_t SW = bk_slice_dwords(ig);  // one slice's accumulators
     uint32_t *const scr = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(lds_raw) + sbytes) +
                           wave * bk_scratch_dwords(ig, spw);
@@ -106,29 +107,32 @@ __global__ void __launch_bounds__(BK_WAVES * 64, BK_MIN_BLOCKS) slice_block_kern
         project_rows<VT, 0, ND, false, 1, true, 1>(vol + (y0 + j0) * rd.L, rd.L, pitch_z, 0, rd.N, rd.R, rd.CT, scr, ig,
                                                 nsl, rd.L, SW, a.b.packed_end);
         wave_lds_sync();
-        // row sides into the store: four values per lane, read together, one store
+        // row sides into the store, four values per lane, read together, one store.  The
+        // chunks of both sides of all nsl slices of a direction are numbered together, so
+        // that short rows still keep every lane busy: chunk c is slice c / cps, then side 0
+        // or 1 (q0 chunks of side 0 first); nsl <= 4.
         StaticFor<0, ND>::run([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int pp = dir_pp(i, G);
+            const int32_t q0 = plen[2 * i] >> 2, cps = q0 + (plen[2 * i + 1] >> 2);  // lens: multiples of 16
+            const SegView v0 = seg_view(scr, ig, i, 0, i == 1, pp), v1 = seg_view(scr, ig, i, 1, i == 1, pp);
+            const int32_t so0 = soff[2 * i], so1 = soff[2 * i + 1], rs0 = rstr[2 * i], rs1 = rstr[2 * i + 1];
+            for (int32_t c = lane; c < cps * nsl; c += 64) {
+                const int32_t sl = (c >= cps) + (c >= 2 * cps) + (c >= 3 * cps);
+                const int32_t r = c - sl * cps;
+                const bool s1 = r >= q0;
+                const int32_t x0 = 4 * (s1 ? r - q0 : r);
+                SegView v = s1 ? v1 : v0;
+                v.row += sl * SW;
+                RV *dst = store + (s1 ? so1 : so0) + (j0 + sl) * (s1 ? rs1 : rs0) + x0;
+                uint32_t e[4];
 #pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                const int s = 2 * i + side;
-                const int32_t len = plen[s];
-                if (len == 0) continue;
-                SegView v = seg_view(scr, ig, i, side, i == 1, pp);
-                for (int sl = 0; sl < nsl; ++sl, v.row += SW) {
-                    RV *dst = store + soff[s] + (j0 + sl) * rstr[s];
-                    for (int32_t x0 = 4 * lane; x0 < len; x0 += 256) {  // len is a multiple of 16
-                        uint32_t e[4];
-#pragma unroll
-                        for (int c = 0; c < 4; ++c)
-                            e[c] = (x0 + c >= v.alo && x0 + c <= v.ahi) ? seg_value(v, x0 + c) : 0u;
-                        if constexpr (sizeof(RV) == 2)
-                            *reinterpret_cast<uint2 *>(dst + x0) = make_uint2(e[0] | e[1] << 16, e[2] | e[3] << 16);
-                        else
-                            *reinterpret_cast<uint4 *>(dst + x0) = make_uint4(e[0], e[1], e[2], e[3]);
-                    }
-                }
+                for (int k = 0; k < 4; ++k)
+                    e[k] = (x0 + k >= v.alo && x0 + k <= v.ahi) ? seg_value(v, x0 + k) : 0u;
+                if constexpr (sizeof(RV) == 2)
+                    *reinterpret_cast<uint2 *>(dst) = make_uint2(e[0] | e[1] << 16, e[2] | e[3] << 16);
+                else
+                    *reinterpret_cast<uint4 *>(dst) = make_uint4(e[0], e[1], e[2], e[3]);
             }
         });
         wave_lds_sync();  // the next group clears this scratch
