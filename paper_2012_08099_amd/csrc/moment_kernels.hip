@@ -138,48 +138,69 @@ __global__ void __launch_bounds__(NT) finish_kernel(FinishArgs a) {
     finish_store(a, vol, m, k, p, num);
 }
 
-// Recombination of batched ROIs: one workgroup per ROI, thread m computes moment m from
-// the ROI's few tiles on its own (no cross-lane sums), with the loads of FIN_BATCH tiles
-// in flight together.
-constexpr int FIN_ROI_THREADS = 128;  // >= n_moments(6) = 84
+// Recombination of batched ROIs: one workgroup per ROI.  Thread t takes the (moment, slot)
+// pairs t, t + FIN_ROI_THREADS, ...: the slot's tiles of the ROI (their loads in flight
+// together) times the slot's coefficient, into LDS; then thread m adds moment m's slot
+// products.  Every pair's loads are issued at once instead of one slot after another.
+constexpr int FIN_ROI_THREADS = 256;
+constexpr int FIN_ROI_SLOTS = 14;            // 2 (K + 1) for K <= 6
+constexpr int FIN_ROI_PAIRS = 84 * FIN_ROI_SLOTS;  // n_moments(6) x slots
 
 template <int NLR>
 __global__ void __launch_bounds__(FIN_ROI_THREADS) finish_roi_kernel(FinishArgs a) {
-    const int vol = blockIdx.x, m = threadIdx.x, K = a.K;
-    if (m >= n_moments(K)) return;  // no barriers below
-    int p, q, r;
-    decode_moment(m, p, q, r);
-    const int k = p + r;
+    __shared__ uint32_t prod[FIN_ROI_PAIRS][NLR];
+    const int vol = blockIdx.x, tid = threadIdx.x, K = a.K;
+    const int nm = n_moments(K), ns = 2 * (K + 1);
     const RoiDesc &rd = a.rois[vol];
     const int ipt = (int)((rd.M + 15) / 16);
-    mw::Int<NLR> num;
-    mw::set_zero(num);
-    int rank = 0;
-    for (int s = 0; s < 14 && s < 2 * (k + 1); ++s) {
-        if (!rd.slot_len[s]) continue;
-        const int d = s >> 1, side = s & 1;
-        const int64_t c = (side == 0 && (k & 1)) ? -c_num[k][p][d] : c_num[k][p][d];
-        const size_t t0 = (size_t)rd.tile0 + (size_t)rank * ipt;
-        ++rank;
-        if (c == 0) continue;
-        for (int b0 = 0; b0 < ipt; b0 += FIN_BATCH) {
-            mw::Int<NLR> v[FIN_BATCH];
+    for (int pr = tid; pr < nm * ns; pr += FIN_ROI_THREADS) {
+        const int m = pr / ns, s = pr - m * ns;
+        int p, q, r;
+        decode_moment(m, p, q, r);
+        const int k = p + r;
+        mw::Int<NLR> v;
+        mw::set_zero(v);
+        if (s < 2 * (k + 1) && rd.slot_len[s]) {
+            const int d = s >> 1, side = s & 1;
+            const int64_t c = (side == 0 && (k & 1)) ? -c_num[k][p][d] : c_num[k][p][d];
+            if (c != 0) {
+                int rank = 0;  // non-empty slots before s: this slot's tiles follow theirs
+                for (int e = 0; e < s; ++e) rank += rd.slot_len[e] != 0;
+                const size_t t0 = (size_t)rd.tile0 + (size_t)rank * ipt;
+                for (int b0 = 0; b0 < ipt; b0 += FIN_BATCH) {
+                    mw::Int<NLR> w[FIN_BATCH];
 #pragma unroll
-            for (int b = 0; b < FIN_BATCH; ++b) {
-                mw::set_zero(v[b]);
-                if (b0 + b < ipt) {
-                    const uint32_t *src = a.part + (((t0 + b0 + b) * (K + 1) + k) * (K + 1) + q) * NLR;
+                    for (int b = 0; b < FIN_BATCH; ++b) {
+                        mw::set_zero(w[b]);
+                        if (b0 + b < ipt) {
+                            const uint32_t *src = a.part + (((t0 + b0 + b) * (K + 1) + k) * (K + 1) + q) * NLR;
 #pragma unroll
-                    for (int l = 0; l < NLR; ++l) v[b].w[l] = src[l];
+                            for (int l = 0; l < NLR; ++l) w[b].w[l] = src[l];
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < FIN_BATCH; ++b) mw::add(v, w[b]);
                 }
+                v = mw::mul_i64(v, c);
             }
-            mw::Int<NLR> sv = v[0];
-#pragma unroll
-            for (int b = 1; b < FIN_BATCH; ++b) mw::add(sv, v[b]);
-            mw::add(num, mw::mul_i64(sv, c));
         }
+#pragma unroll
+        for (int l = 0; l < NLR; ++l) prod[pr][l] = v.w[l];
     }
-    finish_store(a, vol, m, k, p, num);
+    __syncthreads();
+    for (int m = tid; m < nm; m += FIN_ROI_THREADS) {
+        int p, q, r;
+        decode_moment(m, p, q, r);
+        mw::Int<NLR> num;
+        mw::set_zero(num);
+        for (int s = 0; s < ns; ++s) {
+            mw::Int<NLR> o;
+#pragma unroll
+            for (int l = 0; l < NLR; ++l) o.w[l] = prod[m * ns + s][l];
+            mw::add(num, o);
+        }
+        finish_store(a, vol, m, p + r, p, num);
+    }
 }
 
 template <int NLR>
