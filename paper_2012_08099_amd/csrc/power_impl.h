@@ -66,6 +66,59 @@ __device__ __forceinline__ void yweight_store(const PowerArgs &a, const TileInfo
     }
 }
 
+// The same T(tile, k, q) with the (k, q) pairs spread evenly over the T / 16 lane groups
+// (one k per group leaves the group of k = d with K - d + 1 pairs and the last with one).
+// stage_r puts every thread's r(item, k) into rt[k - d][item] (LDS, NLS words each); after
+// a barrier, group g takes pairs [g P / G, (g + 1) P / G) in (k, q) order,
+// P = (K - d + 1)(K - d + 2) / 2: it reads r(item, k), raises it by y^q for the group's
+// first q, then sums and stores as above.
+template <int T, int NLS, int NJ>
+__device__ __forceinline__ void stage_r(int d, int K, const mw::Int<NLS> (&R)[NJ], uint32_t *rt, int tid) {
+    const int ei = tid & 15;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int k = d + (tid >> 4) + (T / 16) * j;
+        if (k > K) break;
+#pragma unroll
+        for (int l = 0; l < NLS; ++l) rt[((k - d) * 16 + ei) * NLS + l] = R[j].w[l];
+    }
+}
+
+template <int T, int NLS, int NLR>
+__device__ __forceinline__ void yweight_store_even(const PowerArgs &a, const TileInfo &ti, int tile, int d,
+                                                   const uint32_t *rt, int tid) {
+    constexpr int NG = T / 16;
+    const int ei = tid & 15, g = tid >> 4, K = a.K;
+    const uint32_t y = (uint32_t)((ti.ybase + ei) / ti.ydiv);
+    const int nk = K - d + 1;
+    const int P = nk * (nk + 1) / 2;
+    const int p0 = g * P / NG, p1 = (g + 1) * P / NG;
+    if (p0 >= p1) return;  // uniform over the lane group
+    int k = d, before = 0;  // pairs of the k below the current one
+    while (before + (K - k + 1) <= p0) {
+        before += K - k + 1;
+        ++k;
+    }
+    int q = p0 - before;
+    for (int pi = p0; pi < p1; ++k, q = 0) {
+        mw::Int<NLS> r;
+#pragma unroll
+        for (int l = 0; l < NLS; ++l) r.w[l] = rt[((k - d) * 16 + ei) * NLS + l];
+        mw::Int<NLR> v = mw::resize<NLR, NLS>(r);  // r >= 0
+        for (int e = 0; e < q; ++e) mw::mul_u32(v, y);
+        uint32_t *dst = a.part + ((size_t)tile * (K + 1) + k) * (K + 1) * NLR;
+        const int qe = K - k < q + (p1 - pi) - 1 ? K - k : q + (p1 - pi) - 1;
+        for (; q <= qe; ++q, ++pi) {
+            mw::Int<NLR> s = v;
+            row16_sum_last(s);
+            if (ei == 15)
+#pragma unroll
+                for (int l = 0; l < NLR; ++l) dst[(size_t)q * NLR + l] = s.w[l];
+            mw::mul_u32(v, y);
+        }
+    }
+}
+
 constexpr int PW_MW = 4;   // waves of the split-contraction kernel
 constexpr int PW_PF = 3;   // K-steps per wave whose loads are in flight together
 constexpr int PW_NTP = 4;  // 16-column tiles per wave and pass (4 P-limbs x 4 tiles x 4 = 64 VGPRs)

@@ -199,7 +199,16 @@ __global__ void __launch_bounds__(MW * 64) power_mfma_kernel(PowerArgs a) {
             }
         }
     }
-    yweight_store<T, NLS, NLR, NJ>(a, ti, blockIdx.x, d, R, threadIdx.x);
+    if constexpr (MW > 1) {
+        // the last reassembly is behind a barrier: its table takes the sums r(item, k)
+        static_assert((KMAX + 1) * 16 * NLS <= 4 * NCT * 256, "r table exceeds the LDS table");
+        uint32_t *rt = reinterpret_cast<uint32_t *>(&ctab[0][0][0]);
+        stage_r<T, NLS, NJ>(d, a.K, R, rt, tid);
+        __syncthreads();
+        yweight_store_even<T, NLS, NLR>(a, ti, blockIdx.x, d, rt, tid);
+    } else {
+        yweight_store<T, NLS, NLR, NJ>(a, ti, blockIdx.x, d, R, threadIdx.x);
+    }
 }
 
 template <int NLS, int NLR>
@@ -289,7 +298,12 @@ __global__ void __launch_bounds__(PW_MW * 64) power_mfma_cols_kernel(PowerArgs a
 #pragma unroll
     for (int j = 0; j < NJ; ++j) mw::set_zero(R[j]);
     reassemble<T, NLS, NJ, PW_CTILES>(a, d, 0, PW_CTILES, ctab, R, threadIdx.x);
-    yweight_store<T, NLS, NLR, NJ>(a, ti, blockIdx.x, d, R, threadIdx.x);
+    __syncthreads();  // every thread has read the table: it takes the sums r(item, k)
+    static_assert((KMAX + 1) * 16 * NLS <= 4 * PW_CTILES * 256, "r table exceeds the LDS table");
+    uint32_t *rt = reinterpret_cast<uint32_t *>(lds);
+    stage_r<T, NLS, NJ>(d, a.K, R, rt, tid);
+    __syncthreads();
+    yweight_store_even<T, NLS, NLR>(a, ti, blockIdx.x, d, rt, tid);
 }
 
 template <int NLS, int NLR>
