@@ -333,7 +333,7 @@ def serve_main(a):
     return 0
 
 
-def rois_leg(n, seed, steps, warmup):
+def rois_leg(n, seed, steps, warmup, tune=True):
     """Batched ROIs: n uint8 sphere-mask ROIs with dims U{8..96}^3 (sizes vary per axis),
     K = 4 (35 exact moments each), all packed in one device buffer.  One step = every
     ROI's moments by one dpm_moments_batched launch sequence; compared with the same ROIs
@@ -351,6 +351,16 @@ def rois_leg(n, seed, steps, warmup):
     packed, rois = dpm.pack_rois(vols, "cuda:0")
     n = len(vols)
     nvox = int(sum(v.size for v in vols))
+    batch_tuning = None
+    if tune:
+        # the batch geometry (fused or separate kernels, slices per wave), measured on this batch
+        from paper_2012_08099_amd import autotune
+        t0 = time.perf_counter()
+        r = autotune.tune_batched(packed, rois, K, reps=10)
+        default = next((c["ms"] for c in r["confirmed"] if (c["fused"], c["units"], c["max_spw"]) == (0, 0, 0)), None)
+        batch_tuning = {"fused": r["best"]["fused"], "units": r["best"]["units"], "max_spw": r["best"]["max_spw"],
+                        "ms_best": r["best"]["ms"], "ms_planner_default": default,
+                        "candidates": len(r["candidates"]), "seconds": time.perf_counter() - t0}
     ws = torch.empty(dpm.batched_workspace_bytes(rois, K), dtype=torch.uint8, device="cuda:0")
     ex = torch.empty((n, dpm.num_moments(K), 2), dtype=torch.int64, device="cuda:0")
     fp = torch.empty((n, dpm.num_moments(K)), dtype=torch.float64, device="cuda:0")
@@ -397,18 +407,18 @@ def rois_leg(n, seed, steps, warmup):
     return {"rois": n, "voxels": nvox, "ms_per_batch": ms_b, "rois_per_s": n / (ms_b / 1e3),
             "voxels_per_s": nvox / (ms_b / 1e3), "hbm_frac_algorithmic": nvox / (ms_b / 1e3) / (HBM_PEAK_GBS * 1e9),
             "plain_launches_ms": ms_p, "speedup_vs_plain": ms_p / ms_b, "stages_ms": stages,
-            "workspace_bytes": int(ws.numel())}
+            "workspace_bytes": int(ws.numel()), "batch_tuning": batch_tuning}
 
 
 def rois_main(a):
-    r = rois_leg(a.requests, a.seed, a.steps, a.warmup)
+    r = rois_leg(a.requests, a.seed, a.steps, a.warmup, tune=not a.no_tune)
     n, nvox, ms_b = r["rois"], r["voxels"], r["ms_per_batch"]
     out = {"metric": "ROIs/s (1000 u8 ROIs U{8..96}^3, orders <= 4)", "value": n / (ms_b / 1e3), "unit": "ROIs/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_b, "higher_is_better": True,
            "dtype": "u8", "data": "synthetic",
            "config": {"workload": f"rois{n}: {n} uint8 sphere-mask ROIs, dims U{{8..96}}^3, {nvox} voxels, K=4"},
            "voxels_per_s": r["voxels_per_s"], "plain_launches_ms": r["plain_launches_ms"],
-           "speedup_vs_plain": r["speedup_vs_plain"], "stages_ms": r["stages_ms"]}
+           "speedup_vs_plain": r["speedup_vs_plain"], "stages_ms": r["stages_ms"], "batch_tuning": r["batch_tuning"]}
     print(json.dumps(out), flush=True)
     return 0
 
@@ -661,7 +671,7 @@ def main(argv=None):
         if K <= 6:
             out["paper_route"] = paper_leg(vols, shape, code, K=4)
             log("paper_route", out["paper_route"])
-        out["rois1000"] = rois_leg(1000, a.seed, 20, 5)
+        out["rois1000"] = rois_leg(1000, a.seed, 20, 5, tune=not a.no_tune)
         log("rois1000", out["rois1000"])
         out["serve_mix"] = serve_leg(a, a.serve_requests, modes=("device",),
                                      ct0=V0 if (gen == "ct" and shape == (512, 512, 512)) else None)["device"]

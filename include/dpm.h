@@ -451,6 +451,33 @@ typedef struct {
 int dpm_tune_set(const int64_t dims[3], dpm_dtype dtype, int max_order, const dpm_tuning *t);
 int dpm_tune_clear(void);
 
+/* Override of the batched call's geometry for batches of order max_order (0-6), for
+ * callers that measured a better one (the package's `autotune.tune_batched` times the
+ * candidates through dpm_moments_batched and installs the fastest).  It changes how the
+ * work is split, never the result.
+ *   fused:   0 = the planner's routing (every ROI whose block of 16 slices fits the fused
+ *            kernel takes it); -1 = every ROI takes the separate kernels (rows in the
+ *            workspace).
+ *   units:   projection units per sub-row that grouping slices per wave aims at;
+ *            0 = the planner's choice (2), else 1-16.
+ *   max_spw: most slices one wave projects together; 0 = the planner's choice (4), or
+ *            1, 2 or 4.
+ * The override applies to every later batched call and workspace query of that order
+ * (query dpm_batched_workspace_bytes after setting it: the separate kernels need rows in
+ * the workspace); cached graphs of earlier calls are not replayed after a change.
+ * Calls already enqueued keep their plan; set it before serving rather than during.
+ * t == NULL removes the override of that order.
+ * Errors: DPM_EINVAL for an order outside [0, 6], fused not 0 or -1, units outside
+ * [0, 16] or max_spw not 0, 1, 2 or 4. */
+typedef struct {
+    int32_t fused;
+    int32_t units;
+    int32_t max_spw;
+    int32_t reserved;
+} dpm_batch_tuning;
+
+int dpm_batch_tune_set(int max_order, const dpm_batch_tuning *t);
+
 #ifdef __cplusplus
 }
 #endif

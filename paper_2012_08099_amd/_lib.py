@@ -63,6 +63,11 @@ class Tuning(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("fused", ctypes.c_int32), ("units", ctypes.c_int32), ("max_spw", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("calls", ctypes.c_int32), ("reserved", ctypes.c_int32), ("ms_project", ctypes.c_double),
                 ("ms_power", ctypes.c_double), ("ms_combine", ctypes.c_double),
@@ -132,6 +137,7 @@ SIGNATURES = {
     "dpm_tune_set": (ctypes.c_int, [ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
                                     ctypes.POINTER(Tuning)]),
     "dpm_tune_clear": (ctypes.c_int, []),
+    "dpm_batch_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(BatchTuning)]),
     "dpm_moments_from_images": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int,
                                                ctypes.c_int, ctypes.POINTER(Out)]),
     "dpm_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,

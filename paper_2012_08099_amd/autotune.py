@@ -16,6 +16,10 @@ next one's projection), requires each candidate's moments to be bit-identical to
 planner's default, installs the fastest with ``dpm_tune_set`` and returns the timings.
 Results can be kept in a JSON file (``save`` / ``load``) keyed by shape, dtype and order,
 and installed again in a later process without re-measuring.
+
+``tune_batched`` does the same for the batched call's geometry (``dpm_batch_tune_set``: fused
+or separate kernels, and how many slices one wave of the fused kernel projects together),
+per order, on a batch the caller supplies.
 """
 from __future__ import annotations
 
@@ -24,7 +28,8 @@ import json
 import os
 
 from . import _lib
-from . import _dims_of_shape, _dtype_code, check, lib, moments_async, num_moments, workspace_bytes
+from . import (_dims_of_shape, _dtype_code, batched_workspace_bytes, check, lib, moments_async, moments_batched,
+               num_moments, workspace_bytes)
 
 Z_SPLITS = (0, 1, 2, 4, 8)        # 0: the planner's choice
 POWER_CHUNKS = (0, 4, 8, 16, -1)  # 0: the planner's choice, -1: whole rows
@@ -128,6 +133,92 @@ def tune(vol, K, reps=10, warmup=2, z_splits=Z_SPLITS, power_chunks=POWER_CHUNKS
     set_tuning(shape, code, K, best["z_splits"], best["power_chunk"], best["waves"])
     return {"key": _key(shape, code, K), "best": best, "candidates": results, "confirmed": confirmed,
             "objective": objective}
+
+
+BATCH_FUSED = (0, -1)    # 0: the planner's routing, -1: separate kernels for every ROI
+BATCH_UNITS = (0, 1, 4)  # 0: the planner's choice (2 units per sub-row)
+BATCH_SPW = (0, 1, 2)    # 0: the planner's choice (at most 4 slices per wave)
+
+
+def set_batch_tuning(K, fused=0, units=0, max_spw=0):
+    """Install a geometry override for batched calls of order K (see dpm_batch_tune_set)."""
+    t = _lib.BatchTuning(int(fused), int(units), int(max_spw))
+    check(lib().dpm_batch_tune_set(int(K), ctypes.byref(t)), "dpm_batch_tune_set")
+
+
+def unset_batch_tuning(K):
+    check(lib().dpm_batch_tune_set(int(K), None), "dpm_batch_tune_set")
+
+
+def tune_batched(packed, rois, K, reps=10, warmup=3, fused=BATCH_FUSED, units=BATCH_UNITS, max_spw=BATCH_SPW,
+                 stream=None, finalists=3, confirm_rounds=3, margin=0.02):
+    """Measure every (fused, units, max_spw) candidate on one batch (``packed`` and ``rois``
+    from ``pack_rois``) and install the fastest for order K.
+
+    Each candidate is timed as a repeated call (graph replays after its first two calls),
+    must give moments bit-identical to the planner's default, and wins only by beating the
+    default by ``margin``, after the same confirmation rounds as ``tune``.  With fused = -1
+    the other two knobs do not apply, so that candidate is timed once.
+
+    Returns {"best": {...}, "candidates": [{"fused", "units", "max_spw", "ms"}, ...],
+    "confirmed": [...]}."""
+    import torch
+    dev = packed.device
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    n = len(rois)
+    nm, nm4 = num_moments(K), num_moments(min(K, 4))
+
+    def run(cand, reps=reps):
+        if cand is None:
+            unset_batch_tuning(K)
+        else:
+            set_batch_tuning(K, *cand)
+        ws = torch.empty(max(batched_workspace_bytes(rois, K), 1), dtype=torch.uint8, device=dev)
+        ex = torch.zeros((n * nm4, 2), dtype=torch.int64, device=dev)
+        fp = torch.zeros(n * nm, dtype=torch.float64, device=dev)
+        for _ in range(warmup):
+            moments_batched(packed, rois, K, ex, fp, ws, stream=st)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(st)
+        for _ in range(reps):
+            moments_batched(packed, rois, K, ex, fp, ws, stream=st)
+        t1.record(st)
+        t1.synchronize()
+        return t0.elapsed_time(t1) / reps, ex.cpu(), fp.cpu()
+
+    try:
+        _, ref_ex, ref_fp = run(None)
+        cands = []
+        for f in fused:
+            for u in (units if f == 0 else (0,)):
+                for s in (max_spw if f == 0 else (0,)):
+                    cands.append((f, u, s))
+        results = []
+        for c in cands:
+            ms, ex, fp = run(c)
+            if not (torch.equal(ex, ref_ex) and torch.equal(fp.view(torch.int64), ref_fp.view(torch.int64))):
+                raise RuntimeError(f"batch tuning candidate fused={c[0]} units={c[1]} max_spw={c[2]} changed the result")
+            results.append({"fused": c[0], "units": c[1], "max_spw": c[2], "ms": ms})
+        trip = lambda r: (r["fused"], r["units"], r["max_spw"])
+        final = [trip(r) for r in sorted(results, key=lambda r: r["ms"])[:max(1, finalists)]]
+        if (0, 0, 0) not in final and (0, 0, 0) in cands:
+            final.append((0, 0, 0))
+        times = {c: [] for c in final}
+        for _ in range(max(1, confirm_rounds)):
+            for c in final:
+                times[c].append(run(c, 2 * reps)[0])
+        confirmed = [{"fused": c[0], "units": c[1], "max_spw": c[2], "ms": sorted(t)[len(t) // 2]}
+                     for c, t in times.items()]
+        best = min(confirmed, key=lambda r: r["ms"])
+        default = next((r for r in confirmed if trip(r) == (0, 0, 0)), None)
+        if default is not None and best["ms"] > default["ms"] * (1.0 - margin):
+            best = default
+    except BaseException:
+        unset_batch_tuning(K)
+        raise
+    set_batch_tuning(K, best["fused"], best["units"], best["max_spw"])
+    return {"best": best, "candidates": results, "confirmed": confirmed}
 
 
 def save(results, path):

@@ -74,6 +74,17 @@ bool fused_allowed() {
 }
 int block_class(int elem, int rowbytes) { return elem == 2 ? 2 : rowbytes == 2 ? 0 : 1; }
 
+// Per-order overrides of the batch geometry (dpm_batch_tune_set), and a generation that
+// every change bumps: cached graphs of an older generation never match again.
+std::mutex g_btune_mu;
+dpm_batch_tuning g_btune[7] = {};
+uint64_t g_btune_gen = 0;
+dpm_batch_tuning batch_tuning(int K, uint64_t *gen) {
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    if (gen) *gen = g_btune_gen;
+    return (K >= 0 && K <= 6) ? g_btune[K] : dpm_batch_tuning{};
+}
+
 // Pinned staging for the descriptor upload, so the call stays asynchronous: a buffer
 // is reused only once the event recorded after its copy has fired.
 struct Staging {
@@ -181,7 +192,10 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
     if (p.lds > 160 * 1024) return DPM_ERANGE;
     int32_t cs[KMAX + 2];
     p.mfma = small_p && p.amax <= 8192 && batched_pow_columns(p.amax, K, cs);
-    const bool fuse_ok = p.mfma && p.nlr == 4 && fused_allowed();
+    const dpm_batch_tuning bt = batch_tuning(K, nullptr);
+    const bool fuse_ok = p.mfma && p.nlr == 4 && fused_allowed() && bt.fused >= 0;
+    const int spw_max = bt.max_spw ? bt.max_spw : 4;  // 1, 2 or 4
+    const int units = bt.units ? bt.units : 2;        // units per sub-row the grouping aims at
     std::vector<char> fz(n, 0);
     int64_t lds_blk_max = 0;
     for (int i = 0; i < n; ++i)
@@ -224,10 +238,11 @@ int bplan(const dpm_roi *rois, int n, int K, BPlan &p) {
                 while (rr < lanes) rr <<= 1;
                 d.R = rr;
             }
-            // slices a wave projects together: enough units for two per sub-row, as far as
-            // the LDS of the batch's largest block allows
+            // slices a wave projects together: enough units for two (or the tuned number)
+            // per sub-row, as far as the LDS of the batch's largest block allows
             const int64_t u1 = (int64_t)d.CT * geoms[i].n_chunks, subrows = 64 / d.R;
-            while (d.spw < 4 && d.spw * u1 < 2 * subrows && bk_lds_bytes(geoms[i], nd, d.rowbytes, 2 * d.spw) <= cap)
+            while (d.spw < spw_max && d.spw * u1 < units * subrows &&
+                   bk_lds_bytes(geoms[i], nd, d.rowbytes, 2 * d.spw) <= cap)
                 d.spw *= 2;
             size_t &cl = p.lds_block[block_class(d.elem, d.rowbytes)];
             cl = std::max(cl, (size_t)bk_lds_bytes(geoms[i], nd, d.rowbytes, d.spw));
@@ -325,12 +340,14 @@ hipError_t enqueue(const BPlan &p, const PowTab &pt, const uint8_t *packed, RoiD
 // descriptors; everything else lives in the caller's buffers, which the key pins.
 struct GraphKey {
     int dev = -1, n = 0, K = 0;
+    uint64_t tune_gen = 0;  // generation of the batch tuning the plan was made with
     const void *packed = nullptr, *exact = nullptr, *fp64 = nullptr, *ws = nullptr;
     size_t ws_bytes = 0;
     std::vector<uint8_t> rois;
     uint64_t hash = 0;
     bool operator==(const GraphKey &o) const {
-        return hash == o.hash && dev == o.dev && n == o.n && K == o.K && packed == o.packed && exact == o.exact &&
+        return hash == o.hash && dev == o.dev && n == o.n && K == o.K && tune_gen == o.tune_gen && packed == o.packed &&
+               exact == o.exact &&
                fp64 == o.fp64 && ws == o.ws && ws_bytes == o.ws_bytes && rois == o.rois;
     }
 };
@@ -363,6 +380,7 @@ uint64_t key_hash(const GraphKey &k) {
     mix(&k.dev, sizeof k.dev);
     mix(&k.n, sizeof k.n);
     mix(&k.K, sizeof k.K);
+    mix(&k.tune_gen, sizeof k.tune_gen);
     mix(&k.packed, sizeof k.packed);
     mix(&k.exact, sizeof k.exact);
     mix(&k.fp64, sizeof k.fp64);
@@ -497,6 +515,17 @@ int dpm_moments_batched(const void *packed, const dpm_roi *rois, int n_rois, int
     return dpm::batched_run(packed, rois, n_rois, max_order, out_device, workspace, ws_bytes, stream, true);
 }
 
+int dpm_batch_tune_set(int max_order, const dpm_batch_tuning *t) {
+    if (max_order < 0 || max_order > 6) return DPM_EINVAL;
+    if (t && (t->fused < -1 || t->fused > 0 || t->units < 0 || t->units > 16 ||
+              (t->max_spw != 0 && t->max_spw != 1 && t->max_spw != 2 && t->max_spw != 4)))
+        return DPM_EINVAL;
+    std::lock_guard<std::mutex> lk(g_btune_mu);
+    g_btune[max_order] = t ? *t : dpm_batch_tuning{};
+    ++g_btune_gen;
+    return DPM_OK;
+}
+
 int dpm_batched_graph_count(void) {
     std::lock_guard<std::mutex> lk(g_graph_mu);
     return (int)g_graphs.size();
@@ -525,6 +554,7 @@ int batched_run(const void *packed, const dpm_roi *rois, int n_rois, int max_ord
         }
         key.n = n_rois;
         key.K = max_order;
+        (void)batch_tuning(max_order, &key.tune_gen);
         key.packed = packed;
         key.exact = out_device->exact;
         key.fp64 = out_device->fp64;

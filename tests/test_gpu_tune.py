@@ -42,3 +42,49 @@ def test_autotune_installs_an_exact_split():
         assert (r3["best"]["z_splits"], r3["best"]["power_chunk"], r3["best"]["waves"]) == (0, 0, 0)
     finally:
         autotune.clear()
+
+
+def test_batch_tuning_installs_an_exact_geometry():
+    """autotune.tune_batched: every batch geometry (fused or separate kernels, units per
+    sub-row, slices per wave) gives the default's moments bit for bit, and the installed
+    one and the forced separate route still match the exact direct sums of eq. (2)."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import oracle.native as onative
+    import paper_2012_08099_amd as dpm
+    from paper_2012_08099_amd import autotune
+    K = 4
+    rng = np.random.default_rng(7)
+    rois = [synth.uniform_volume((int(rng.integers(4, 40)), int(rng.integers(1, 40)), int(rng.integers(3, 60))),
+                                 np.uint8 if i % 3 else np.uint16, seed=100 + i) for i in range(40)]
+    print("tune_batched 40 ROIs K=4", flush=True)
+    sys.stdout.flush()
+    packed, desc = dpm.pack_rois(rois, "cuda:0")
+    n, nm = len(rois), dpm.num_moments(K)
+
+    def call():
+        ex = torch.zeros((n * nm, 2), dtype=torch.int64, device="cuda:0")
+        fp = torch.zeros(n * nm, dtype=torch.float64, device="cuda:0")
+        ws = torch.empty(max(dpm.batched_workspace_bytes(desc, K), 1), dtype=torch.uint8, device="cuda:0")
+        dpm.moments_batched(packed, desc, K, ex, fp, ws)
+        torch.cuda.synchronize()
+        exact = dpm._exact_from_tensor(ex.cpu())
+        fpn = fp.cpu().numpy()
+        for i, V in enumerate(rois):
+            got = dpm.Moments(K, exact[i * nm:(i + 1) * nm], fpn[i * nm:(i + 1) * nm])
+            assert_moments_equal(got, onative.moments_hoisted(V, K), K, f"roi {i} {V.shape}")
+
+    try:
+        r = autotune.tune_batched(packed, desc, K, reps=3, warmup=3, confirm_rounds=1)
+        assert len(r["candidates"]) == 10 and all(c["ms"] > 0 for c in r["candidates"])
+        call()
+        autotune.set_batch_tuning(K, fused=-1)
+        call()
+        autotune.set_batch_tuning(K, fused=0, units=1, max_spw=1)
+        call()
+        # no candidate beats the default by the whole default time: the default stays
+        r2 = autotune.tune_batched(packed, desc, K, reps=2, warmup=3, units=(0, 4), max_spw=(0,), confirm_rounds=1,
+                                   margin=1.0)
+        assert (r2["best"]["fused"], r2["best"]["units"], r2["best"]["max_spw"]) == (0, 0, 0)
+    finally:
+        autotune.unset_batch_tuning(K)

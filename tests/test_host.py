@@ -248,6 +248,39 @@ def test_batched_plan_takes_the_fused_kernel_when_blocks_fit(lib, monkeypatch):
     assert b - a >= 4 * 33 * 17                # at least one int32 per voxel row of its slices
 
 
+def test_batch_tuning_routes_and_validates(lib, monkeypatch):
+    """dpm_batch_tune_set: fused = -1 sends an order's batches to the separate kernels (their
+    row buffer shows in the workspace, as with DPM_BATCH_FUSED=0), other orders keep the
+    planner's routing, NULL restores it, and values outside the documented ranges are
+    refused."""
+    from paper_2012_08099_amd import _lib
+    monkeypatch.delenv("DPM_BATCH_FUSED", raising=False)
+    small = _rois([(20, 33, 17, 1), (96, 96, 96, 1), (40, 5, 21, 2)])
+    fused4, fused3 = lib.dpm_batched_workspace_bytes(small, 3, 4), lib.dpm_batched_workspace_bytes(small, 3, 3)
+    monkeypatch.setenv("DPM_BATCH_FUSED", "0")
+    separate4 = lib.dpm_batched_workspace_bytes(small, 3, 4)
+    monkeypatch.delenv("DPM_BATCH_FUSED")
+    try:
+        assert lib.dpm_batch_tune_set(4, ctypes.byref(_lib.BatchTuning(-1, 0, 0))) == 0
+        assert lib.dpm_batched_workspace_bytes(small, 3, 4) == separate4 > fused4
+        assert lib.dpm_batched_workspace_bytes(small, 3, 3) == fused3
+        # the geometry knobs keep the fused routing (slices per wave live in LDS, not the workspace)
+        assert lib.dpm_batch_tune_set(4, ctypes.byref(_lib.BatchTuning(0, 4, 2))) == 0
+        assert lib.dpm_batched_workspace_bytes(small, 3, 4) == fused4
+        assert lib.dpm_batch_tune_set(4, None) == 0
+        assert lib.dpm_batched_workspace_bytes(small, 3, 4) == fused4
+        for order, bad in ((7, _lib.BatchTuning(0, 0, 0)), (-1, _lib.BatchTuning(0, 0, 0)),
+                           (4, _lib.BatchTuning(1, 0, 0)), (4, _lib.BatchTuning(-2, 0, 0)),
+                           (4, _lib.BatchTuning(0, 17, 0)), (4, _lib.BatchTuning(0, -1, 0)),
+                           (4, _lib.BatchTuning(0, 0, 3)), (4, _lib.BatchTuning(0, 0, 8))):
+            assert lib.dpm_batch_tune_set(order, ctypes.byref(bad)) == -1
+        for good in (_lib.BatchTuning(0, 1, 1), _lib.BatchTuning(0, 16, 4), _lib.BatchTuning(-1, 0, 2)):
+            assert lib.dpm_batch_tune_set(6, ctypes.byref(good)) == 0
+    finally:
+        for k in range(7):
+            lib.dpm_batch_tune_set(k, None)
+
+
 def test_tuning_overrides_change_the_plan_only(lib):
     """dpm_tune_set: a per-shape override of the work split shows in dpm_plan (z-splits,
     power tiles) and is removed by t=NULL / dpm_tune_clear; bad values are refused."""
