@@ -119,8 +119,11 @@ __device__ constexpr bool slot_used(int s) {
 }
 
 // safe_end (general loads only, may be null): every byte before it may be read, so a lane
-// whose dwords all lie before it loads them without a check per dword
-template <typename VT, bool FAST>
+// whose dwords all lie before it loads them without a check per dword.  NTL (whole-row
+// loads): non-temporal, for a volume read once; plain where sibling workgroups of the same
+// XCD read the same rows after this one (the direction groups of one launch), so that the
+// lines stay in L2 for them.
+template <typename VT, bool FAST, bool NTL = true>
 __device__ __forceinline__ typename VecOf<VT>::type load_lane(const VT *row, int64_t x0, int64_t L, bool in,
                                                               const uint8_t *safe_end = nullptr) {
     using Vec = typename VecOf<VT>::type;
@@ -128,8 +131,11 @@ __device__ __forceinline__ typename VecOf<VT>::type load_lane(const VT *row, int
     constexpr int G = VecOf<VT>::G;
     Vec v{};
     if constexpr (FAST) {
-        // streamed once: non-temporal, so it does not evict the small shared tables
-        const Raw r = __builtin_nontemporal_load(reinterpret_cast<const Raw *>(row + x0));
+        Raw r;
+        if constexpr (NTL)  // streamed once: does not evict the small shared tables
+            r = __builtin_nontemporal_load(reinterpret_cast<const Raw *>(row + x0));
+        else
+            r = *reinterpret_cast<const Raw *>(row + x0);
         __builtin_memcpy(&v, &r, sizeof(Vec));
     } else if (in) {
         // Any alignment, ragged row end: the aligned dwords that hold at least one
@@ -192,7 +198,8 @@ struct GroupTraits {
 // MS: the item is nsl consecutive slices (slice s at slice + s pitch_y, its row
 // accumulators at lds + s sw), whose units the sub-rows share: small slices then keep
 // more of the wave busy.
-template <typename VT, int D0, int ND, bool FAST, int NW, bool MS = false, int NBU = SLICE_UNITS_IN_FLIGHT>
+template <typename VT, int D0, int ND, bool FAST, int NW, bool MS = false, int NBU = SLICE_UNITS_IN_FLIGHT,
+          bool NTL = true>
 __device__ __forceinline__ void project_rows(const VT *__restrict__ slice, int64_t L, int64_t pitch_z, int64_t zs,
                              int64_t ze, int R, int CT, uint32_t *lds, const ItemGeom &ig, int nsl = 1,
                              int64_t pitch_y = 0, int32_t sw = 0, const uint8_t *safe_end = nullptr) {
@@ -278,7 +285,7 @@ __device__ __forceinline__ void project_rows(const VT *__restrict__ slice, int64
         StaticFor<0, T>::run([&](auto tc) {
             constexpr int t = decltype(tc)::value;
             if constexpr (FAST) {
-                buf[t] = load_lane<VT, true>(q.p + t * pitch_z, 0, L, true);
+                buf[t] = load_lane<VT, true, NTL>(q.p + t * pitch_z, 0, L, true);
             } else {
                 const int64_t z = zc0 + t;
                 const bool in = valid && z < ze;
@@ -718,7 +725,7 @@ __device__ __forceinline__ uint32_t seg_value(const SegView &v, int32_t a) {
 }
 
 // ------------------------------------------------------------ per-item driver
-template <typename VT, int D0, int ND, bool FAST, bool CHAIN, int NW>
+template <typename VT, int D0, int ND, bool FAST, bool CHAIN, int NW, bool NTL = true>
 __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int64_t pitch_y,
                            int64_t pitch_z, int64_t y, int64_t zs, int64_t ze, int R, int CT,
                            int32_t *__restrict__ rows_out, const int32_t *slot_off, const int32_t *slot_len,
@@ -767,7 +774,8 @@ __device__ void slice_item(const VT *__restrict__ vol, int64_t L, int64_t N, int
         static_assert(FAST && D0 == 0, "chained windows: first group, exact rows only");
         project_rows_chain<VT, ND, NW>(vol + y * pitch_y, L, pitch_z, zs, ze, CT, lds, ig);
     } else {
-        project_rows<VT, D0, ND, FAST, NW>(vol + y * pitch_y, L, pitch_z, zs, ze, R, CT, lds, ig);
+        project_rows<VT, D0, ND, FAST, NW, false, SLICE_UNITS_IN_FLIGHT, NTL>(vol + y * pitch_y, L, pitch_z, zs, ze, R,
+                                                                            CT, lds, ig);
     }
     __syncthreads();
 
@@ -828,7 +836,8 @@ slice_kernel(SliceArgs a) {
 // to the 8 XCDs round-robin in index order), so the item's rows come from HBM about once
 // and to the siblings from that XCD's L2 or the MALL.  Block b: XCD x = b % 8, local
 // index l = b / 8; item = (l / NG) * 8 + x, group = l % NG.  Moments only (no images),
-// whole-row loads only.
+// whole-row loads only, and plain (not non-temporal) loads, so that the lines the first
+// sibling brings in stay in L2 for the others.
 constexpr int NXCD = 8;
 
 template <typename VT, int ND1, int ND2>
@@ -848,13 +857,13 @@ slice_groups_kernel(SliceArgs a, int items) {
     const VT *vol = reinterpret_cast<const VT *>(a.vol);
     int32_t *rows = a.rows + item * a.rl.row_stride;
     if (g == 0)
-        slice_item<VT, 0, 7, true, false, NW>(vol, a.L, a.N, a.pitch_y, a.pitch_z, y, zs, ze, a.R, a.CT, rows,
+        slice_item<VT, 0, 7, true, false, NW, false>(vol, a.L, a.N, a.pitch_y, a.pitch_z, y, zs, ze, a.R, a.CT, rows,
                                               a.rl.slot_off, a.rl.slot_len, nullptr, nullptr, nullptr, lds, ig);
     else if (g == 1)
-        slice_item<VT, 7, ND1, true, false, NW>(vol, a.L, a.N, a.pitch_y, a.pitch_z, y, zs, ze, a.R, a.CT, rows,
+        slice_item<VT, 7, ND1, true, false, NW, false>(vol, a.L, a.N, a.pitch_y, a.pitch_z, y, zs, ze, a.R, a.CT, rows,
                                                 a.rl.slot_off, a.rl.slot_len, nullptr, nullptr, nullptr, lds, ig);
     else if constexpr (ND2 > 0)
-        slice_item<VT, 12, ND2, true, false, NW>(vol, a.L, a.N, a.pitch_y, a.pitch_z, y, zs, ze, a.R, a.CT, rows,
+        slice_item<VT, 12, ND2, true, false, NW, false>(vol, a.L, a.N, a.pitch_y, a.pitch_z, y, zs, ze, a.R, a.CT, rows,
                                                  a.rl.slot_off, a.rl.slot_len, nullptr, nullptr, nullptr, lds, ig);
 }
 
