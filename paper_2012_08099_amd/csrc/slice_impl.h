@@ -839,14 +839,20 @@ slice_kernel(SliceArgs a) {
 // whole-row loads only, and plain (not non-temporal) loads, so that the lines the first
 // sibling brings in stay in L2 for the others.
 constexpr int NXCD = 8;
+// Waves per workgroup of the one-launch groups kernel: its LDS (the widest group's row
+// accumulators, about 58 KB at 512^3) leaves room for two workgroups per CU, so eight
+// waves each are what keeps four waves on every SIMD.
+#ifndef GROUPS_WAVES
+#define GROUPS_WAVES 8
+#endif
 
 template <typename VT, int ND1, int ND2>
-__global__ void __launch_bounds__(slice_waves((int)sizeof(VT)) * 64)
+__global__ void __launch_bounds__(GROUPS_WAVES * 64)
 slice_groups_kernel(SliceArgs a, int items) {
     extern __shared__ uint32_t lds[];
     __shared__ ItemGeom ig;
     constexpr int NG = ND2 > 0 ? 3 : 2;
-    constexpr int NW = slice_waves((int)sizeof(VT));
+    constexpr int NW = GROUPS_WAVES;
     const int b = blockIdx.x, x = b % NXCD, l = b / NXCD;
     const int64_t item = (int64_t)(l / NG) * NXCD + x;
     const int g = l % NG;
@@ -877,7 +883,7 @@ hipError_t launch_groups_one(const SliceArgs &a, int items, size_t lds, hipStrea
     }
     constexpr int NG = ND2 > 0 ? 3 : 2;
     const int64_t blocks = (int64_t)((items + NXCD - 1) / NXCD) * NXCD * NG;
-    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(slice_waves((int)sizeof(VT)) * 64), lds, st, a, items);
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(GROUPS_WAVES * 64), lds, st, a, items);
     return hipGetLastError();
 }
 
